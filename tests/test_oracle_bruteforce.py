@@ -1,0 +1,201 @@
+"""Brute-force cross-check of the vectorised oracle on tiny grids (no GPU).
+
+A per-cell, per-interface loop over plain Python scalars, with its own ghost
+index map, its own flux functions, a complex-step Jacobian and eigenvectors
+from ``numpy.linalg.eig`` rescaled to the stated normalisation. It reuses only
+the oracle's scalar formula functions (which the coefficient pins check), so
+it tests the array plumbing of the oracle: padding, slicing offsets, the
+characteristic projections, the axis handling of the y-sweep and the residual
+assembly of (odeH)/(ode2H).
+"""
+import cmath
+
+import numpy as np
+import pytest
+
+from oracle import hweno as O
+from paper_2411_11229_amd import workloads as WL
+
+G = 1.4
+
+
+def bf_flux(sysname, u, d, adv=(1.0, 1.0)):
+    if sysname == 'advection':
+        return [adv[d] * u[0]]
+    if sysname == 'burgers':
+        return [0.5 * u[0] * u[0]]
+    if len(u) == 3:
+        r, m, E = u
+        p = (G - 1) * (E - 0.5 * m * m / r)
+        return [m, m * m / r + p, m / r * (E + p)]
+    r, m, n, E = u
+    p = (G - 1) * (E - 0.5 * (m * m + n * n) / r)
+    if d == 0:
+        return [m, m * m / r + p, m * n / r, m / r * (E + p)]
+    return [n, m * n / r, n * n / r + p, n / r * (E + p)]
+
+
+def bf_jac(sysname, u, d, adv):
+    nc = len(u)
+    J = np.zeros((nc, nc))
+    for j in range(nc):
+        uc = [complex(x) for x in u]
+        uc[j] += 1e-30j
+        f = bf_flux(sysname, uc, d, adv)
+        J[:, j] = [z.imag / 1e-30 for z in f]
+    return J
+
+
+def bf_eigvecs(u, d):
+    """Right eigenvectors of the Jacobian, scaled like the textbook set:
+    acoustic and entropy columns have first entry 1; in 2D the shear column
+    has first entry 0 and unit transverse momentum entry, and the entropy
+    column carries the transverse velocity in that entry."""
+    nc = len(u)
+    J = bf_jac('euler', u, d, None)
+    lam, vec = np.linalg.eig(J)
+    lam, vec = lam.real, vec.real
+    order = np.argsort(lam)
+    lam, vec = lam[order], vec[:, order]
+    R = np.zeros((nc, nc))
+    R[:, 0] = vec[:, 0] / vec[0, 0]
+    R[:, -1] = vec[:, -1] / vec[0, -1]
+    if nc == 3:
+        R[:, 1] = vec[:, 1] / vec[0, 1]
+        return R
+    # basis of the double eigenvalue's space: null space of J - lam I by SVD
+    _, _, vh = np.linalg.svd(J - 0.5 * (lam[1] + lam[2]) * np.eye(nc))
+    E = vh[-2:, :].T
+    t = 2 if d == 0 else 1                  # transverse momentum entry
+    vt = u[t] / u[0]
+    a = np.linalg.solve(E[[0, t], :], [1.0, vt])
+    b = np.linalg.solve(E[[0, t], :], [0.0, 1.0])
+    R[:, 1] = E @ a
+    R[:, 2] = E @ b
+    return R
+
+
+def mapidx(i, n, lo, hi):
+    if 0 <= i < n:
+        return i
+    side = lo if i < 0 else hi
+    return i % n if side == 'periodic' else min(max(i, 0), n - 1)
+
+
+def bf_line(sysname, d, Uc, Ac, Bc, n, h, alpha, bc, lg, ld, eps, adv):
+    """One grid line. Uc(i)/Ac(i)/Bc(i) return the component lists at cell i
+    (any integer; ghost mapping applied here)."""
+    get = lambda F, i: F(mapidx(i, n, bc[0], bc[1]))
+    nc = len(Uc(0))
+    uR, uL, vR, vL = {}, {}, {}, {}
+    vt = {}
+    for i in range(-1, n + 1):
+        um, u0, up = get(Uc, i - 1), get(Uc, i), get(Uc, i + 1)
+        am, ap = get(Ac, i - 1), get(Ac, i + 1)
+        if sysname == 'euler':
+            R = bf_eigvecs(u0, d)
+            L = np.linalg.inv(R)
+            pr = lambda v: list(L @ np.array(v))
+            wm, w0, wp, qm, qp = pr(um), pr(u0), pr(up), pr(am), pr(ap)
+        else:
+            R = np.eye(1)
+            wm, w0, wp, qm, qp = um, u0, up, am, ap
+        cr, cl, ct = [], [], []
+        for k in range(nc):
+            r_, l_, _, _, t_ = O.hweno_cell(wm[k], w0[k], wp[k], qm[k], qp[k], h, lg, ld, eps)
+            cr.append(r_), cl.append(l_), ct.append(t_)
+        uR[i], uL[i], vt[i] = list(R @ cr), list(R @ cl), list(R @ ct)
+        vR[i], vL[i] = [], []
+        for k in range(nc):
+            _, _, a_, b_, _ = O.hweno_cell(um[k], u0[k], up[k], am[k], ap[k], h, lg, ld, eps)
+            vR[i].append(a_), vL[i].append(b_)
+    f = {i: bf_flux(sysname, get(Uc, i), d, adv) for i in range(-2, n + 2)}
+    hh = {i: list(bf_jac(sysname, get(Uc, i), d, adv) @ np.array(get(Ac, i))) for i in range(-2, n + 2)}
+    ee = None
+    if Bc is not None:
+        ee = {i: list(bf_jac(sysname, get(Uc, i), d, adv) @ np.array(get(Bc, i))) for i in range(-2, n + 2)}
+    Fh, Hh, Eh = {}, {}, {}
+    for k in range(-1, n):
+        um_, up_ = uR[k], uL[k + 1]
+        vm_, vp_ = vR[k], vL[k + 1]
+        fm, fp = bf_flux(sysname, um_, d, adv), bf_flux(sysname, up_, d, adv)
+        hm = list(bf_jac(sysname, um_, d, adv) @ np.array(vm_))
+        hp = list(bf_jac(sysname, up_, d, adv) @ np.array(vp_))
+        Fh[k], Hh[k], Eh[k] = [], [], []
+        for c in range(nc):
+            Df, Dh = O.central_D(f[k - 1][c], f[k][c], f[k + 1][c], f[k + 2][c],
+                                 hh[k - 1][c], hh[k + 2][c], h)
+            Fh[k].append(0.5 * (fm[c] + fp[c] - alpha * (up_[c] - um_[c])) + Df)
+            Hh[k].append(0.5 * (hm[c] + hp[c] - alpha * (vp_[c] - vm_[c])) + Dh)
+            if ee is not None:
+                Eh[k].append((-ee[k - 1][c] + 7 * ee[k][c] + 7 * ee[k + 1][c] - ee[k + 2][c]) / 12)
+    RU = [[-(Fh[i][c] - Fh[i - 1][c]) / h for c in range(nc)] for i in range(n)]
+    RA = [[-(Hh[i][c] - Hh[i - 1][c]) / h for c in range(nc)] for i in range(n)]
+    RB = [[-(Eh[i][c] - Eh[i - 1][c]) / h for c in range(nc)] for i in range(n)] if ee else None
+    return RU, RA, RB, [vt[i] for i in range(n)]
+
+
+def bf_rhs(w, alpha, lg, ld, eps=1e-10):
+    nc = w.U.shape[0]
+    adv = (w.adv_a, w.adv_b)
+    if w.dim == 1:
+        col = lambda F: (lambda i: [F[c, i] for c in range(nc)])
+        RU, RA, _, vt = bf_line(w.system, 0, col(w.U), col(w.V), None, w.nx, w.dx, alpha[0],
+                                w.bc[0:2], lg, ld, eps, adv)
+        T = lambda L: np.array(L).T
+        return T(RU), T(RA), None, T(vt), None
+    ny, nx = w.ny, w.nx
+    L1, L2, L3 = (np.zeros_like(w.U) for _ in range(3))
+    vt, wt = np.zeros_like(w.U), np.zeros_like(w.U)
+    for j in range(ny):
+        row = lambda F: (lambda i: [F[c, j, i] for c in range(nc)])
+        RU, RA, RB, t = bf_line(w.system, 0, row(w.U), row(w.V), row(w.W), nx, w.dx, alpha[0],
+                                w.bc[0:2], lg, ld, eps, adv)
+        L1[:, j, :] += np.array(RU).T
+        L2[:, j, :] += np.array(RA).T
+        L3[:, j, :] += np.array(RB).T
+        vt[:, j, :] = np.array(t).T
+    for i in range(nx):
+        colf = lambda F: (lambda k: [F[c, k, i] for c in range(nc)])
+        RU, RA, RB, t = bf_line(w.system, 1, colf(w.U), colf(w.W), colf(w.V), ny, w.dy, alpha[1],
+                                w.bc[2:4], lg, ld, eps, adv)
+        L1[:, :, i] += np.array(RU).T
+        L3[:, :, i] += np.array(RA).T
+        L2[:, :, i] += np.array(RB).T
+        wt[:, :, i] = np.array(t).T
+    return L1, L2, L3, vt, wt
+
+
+def _cases():
+    out = []
+    for bc in ('periodic', 'transmissive'):
+        w = WL.random_smooth_1d(9, 'burgers', seed=11, bc=bc)
+        out.append((f'burgers1d-{bc}', w))
+        w = WL.random_smooth_1d(10, 'advection', seed=12, bc=bc)
+        out.append((f'adv1d-{bc}', w))
+        w = WL.random_smooth_1d(8, 'euler', seed=13, bc=bc)
+        out.append((f'euler1d-{bc}', w))
+    w = WL.euler1d_riemann_sine(11, seed=2003)
+    out.append(('euler1d-riemann', w))
+    w = WL.euler2d_smooth(6, seed=3001, ny=7)
+    out.append(('euler2d-smooth', w))
+    w = WL.euler2d_quadrants(6, seed=4001, ny=5)
+    out.append(('euler2d-quadrants', w))
+    w = WL.paper_burgers2d(6)
+    w.W = w.W * 0.7 + 0.1
+    out.append(('burgers2d', w))
+    return out
+
+
+@pytest.mark.parametrize("name,w", _cases(), ids=[c[0] for c in _cases()])
+def test_vectorised_oracle_matches_brute_force(name, w):
+    prob = O.Problem(**w.problem_kwargs())
+    alpha = O.max_speed(prob, w.U)
+    ref = bf_rhs(w, alpha, prob.linear_gamma, prob.linear_d)
+    got = O.rhs(prob, w.U, w.V, w.W, alpha)
+    for a, b in zip(got, ref):
+        if a is None:
+            assert b is None
+            continue
+        scale = max(1.0, np.max(np.abs(b)))
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * scale)

@@ -1,0 +1,156 @@
+"""Exactness and invariant pins of the oracle (no GPU).
+
+* Hermite exactness with linear weights (section 2.1): quartic data are
+  reproduced exactly at both faces and the centre.
+* Consistency for nonlinear weights: linear data are exact for any weights;
+  constant data give the linear weights exactly (beta = tau = 0).
+* Conservation: with periodic boundaries the telescoping sum of (odeH) /
+  (ode2H) keeps sum(u) of every component at round-off over RK3 steps.
+* Nonlinear weights tend to the linear ones on smooth data as N grows.
+"""
+import math
+
+import numpy as np
+import numpy.polynomial.polynomial as P
+import pytest
+
+from oracle import hweno as O
+from paper_2411_11229_amd import workloads as WL
+
+RNG = np.random.default_rng(777)
+LIN_G = (0.95, 0.025, 0.025)
+LIN_D = (0.9, 0.05, 0.05)
+
+
+def _quartic_samples(dx, n=6):
+    c = RNG.normal(size=(5, n))
+    xi = RNG.uniform(-3, 3, size=n)
+    pts = xi[None, :] + dx * np.array([-1.0, 0.0, 1.0])[:, None]
+    val = np.stack([P.polyval(pts[k], c, tensor=False) for k in range(3)])
+    der = np.stack([P.polyval(pts[k], P.polyder(c), tensor=False) for k in range(3)])
+    return c, xi, val, der
+
+
+def test_hermite_exactness_with_linear_weights():
+    """P1: with eps so large that tau/(beta+eps) vanishes, omega = linear
+    weights and the gamma-combination collapses to p0, which is exact for
+    quartics: u at both faces, p0' at the faces and the centre."""
+    dx = 0.3
+    c, xi, val, der = _quartic_samples(dx)
+    uR, uL, vR, vL, vt = O.hweno_cell(val[0], val[1], val[2], der[0], der[2], dx,
+                                      LIN_G, LIN_D, 1e300)
+    q = lambda x: P.polyval(x, c, tensor=False)
+    dq = lambda x: P.polyval(x, P.polyder(c), tensor=False)
+    np.testing.assert_allclose(uR, q(xi + dx / 2), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(uL, q(xi - dx / 2), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(vR, dq(xi + dx / 2), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(vL, dq(xi - dx / 2), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(vt, dq(xi), rtol=1e-11, atol=1e-11)
+
+
+def test_linear_data_exact_for_nonlinear_weights():
+    """P2: u = a + b x, v = b makes every candidate exact, so the result is
+    exact whatever the (nonlinear, default-eps) weights are."""
+    a, b = RNG.normal(size=(2, 8))
+    xi = RNG.uniform(-2, 2, size=8)
+    dx = 0.17
+    u = lambda x: a + b * x
+    uR, uL, vR, vL, vt = O.hweno_cell(u(xi - dx), u(xi), u(xi + dx), b, b, dx, LIN_G, LIN_D, 1e-10)
+    np.testing.assert_allclose(uR, u(xi + dx / 2), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(uL, u(xi - dx / 2), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(vR, b, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(vL, b, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(vt, b, rtol=1e-12, atol=1e-12)
+
+
+def test_constant_data_gives_linear_weights_exactly():
+    b0, b1, b2 = O.smoothness_indicators(2.5, 2.5, 2.5, 0.0, 0.0, 0.1)
+    assert b0 == b1 == b2 == 0.0
+    w = O.nonlinear_weights(b0, b1, b2, LIN_G, 1e-10)
+    assert w == pytest.approx(LIN_G, abs=0, rel=1e-15)
+
+
+def test_weights_pick_smooth_stencil_at_a_jump():
+    """At a jump between x_i and x_{i+1}, p2 crosses it and must be
+    down-weighted against p1 (the essentially non-oscillatory property)."""
+    b = O.smoothness_indicators(1.0, 1.0, 0.0, 0.0, 0.0, 0.1)
+    w = O.nonlinear_weights(*b, LIN_G, 1e-10)
+    assert w[1] > 0.99 and w[2] < 1e-6
+
+
+@pytest.mark.parametrize("case", ["burgers1d", "euler1d", "euler2d", "burgers2d", "adv2d"])
+def test_periodic_conservation(case):
+    """P4: sum(u) of every component is invariant to round-off (telescoping
+    flux differences of (odeH)/(ode2H) over periodic cells)."""
+    if case == "burgers1d":
+        w = WL.random_smooth_1d(24, 'burgers', seed=3)
+    elif case == "euler1d":
+        w = WL.random_smooth_1d(24, 'euler', seed=4)
+    elif case == "euler2d":
+        w = WL.euler2d_smooth(12, seed=5)
+    elif case == "burgers2d":
+        w = WL.paper_burgers2d(12)
+    else:
+        w = WL.paper_burgers2d(12)
+        w.system = 'advection'
+        w.adv_a, w.adv_b = 0.7, -1.3
+    prob = O.Problem(**w.problem_kwargs())
+    U, V, W, log = O.run(prob, w.U, w.V, w.W, t_end=10.0, max_steps=6)
+    axes = tuple(range(1, w.U.ndim))
+    s0, s1 = w.U.sum(axis=axes), U.sum(axis=axes)
+    scale = np.abs(w.U).sum(axis=axes)
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s0, s1)
+    # v is not conserved: the modified derivative replaces it in the RK base
+    assert np.any(np.abs(V.sum(axis=axes) - w.V.sum(axis=axes)) > 0)
+
+
+def test_nonlinear_weights_tend_to_linear_on_smooth_data():
+    """P5: max |omega^gamma - gamma| over the cells of u = 0.5 + sin(pi x) on
+    [0,2] decays monotonically with N and is below 1e-3 from N = 160 on."""
+    devs = []
+    for n in (20, 40, 80, 160, 320, 640):
+        x, h = WL.centres(n, 0.0, 2.0)
+        u = 0.5 + np.sin(math.pi * x)
+        v = math.pi * np.cos(math.pi * x)
+        um, up = np.roll(u, 1), np.roll(u, -1)
+        vm, vp = np.roll(v, 1), np.roll(v, -1)
+        b = O.smoothness_indicators(um, u, up, vm, vp, h)
+        w = O.nonlinear_weights(*b, LIN_G, 1e-10)
+        devs.append(max(np.max(np.abs(w[k] - LIN_G[k])) for k in range(3)))
+    assert all(devs[k + 1] < devs[k] for k in range(2, len(devs) - 1)), devs
+    assert devs[3] < 1e-3 and devs[-1] < 1e-6, devs
+
+
+def test_fifth_order_convergence_advection():
+    """P6: linear advection of the seeded C1 data to T = 2 (exact = u0) with
+    the accuracy time step; every L-infinity order from N = 40 on is >= 4.5."""
+    errs, ns = [], (20, 40, 80, 160)
+    for n in ns:
+        w = WL.advection1d_modes(n, seed=1000)
+        prob = O.Problem(**w.problem_kwargs())
+        U, _, _, _ = O.run(prob, w.U, w.V, None, w.t_end, rule='accuracy')
+        errs.append(np.max(np.abs(U - w.U)))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
+    assert all(o >= 4.5 for o in orders[1:]), (errs, orders)
+
+
+def test_mirror_left_face_matches_direct_formula():
+    """The mirrored procedure for u^+_{i-1/2} equals the explicit left-face
+    polynomials (p0, p1, p2 evaluated at x_{i-1/2}) combined with the same
+    weights, which holds because gamma1 = gamma2."""
+    um, u0, up, vm, vp = RNG.normal(size=(5, 10))
+    dx = 0.2
+    c = np.stack([np.linalg.solve(
+        np.array([[1, -1, 1, -1, 1], [1, 0, 0, 0, 0], [1, 1, 1, 1, 1],
+                  [0, 1, -2, 3, -4], [0, 1, 2, 3, 4]], float),
+        np.array([um[k], u0[k], up[k], dx * vm[k], dx * vp[k]])) for k in range(10)], axis=1)
+    p0 = P.polyval(-0.5, c)
+    p1 = 0.5 * (um + u0)
+    p2 = 1.5 * u0 - 0.5 * up
+    b = O.smoothness_indicators(um, u0, up, vm, vp, dx)
+    w = O.nonlinear_weights(*b, LIN_G, 1e-10)
+    direct = w[0] * (p0 / LIN_G[0] - LIN_G[1] / LIN_G[0] * p1 - LIN_G[2] / LIN_G[0] * p2) \
+        + w[1] * p1 + w[2] * p2
+    _, uL, _, vL, _ = O.hweno_cell(um, u0, up, vm, vp, dx, LIN_G, LIN_D, 1e-10)
+    np.testing.assert_allclose(uL, direct, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(vL, P.polyval(-0.5, P.polyder(c)) / dx, rtol=1e-11, atol=1e-11)
