@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the HWENO-I hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2D Euler,
+2048 x 2048 cells on [0,1]^2, seeded four-quadrant Riemann data, transmissive
+boundaries, production time step (CFL 0.6) from the fused max-wave-speed
+reduction every step. A "step" is one full SSP-RK3 step: wave-speed
+reduction, time step, three fused stage kernels. Inputs are resident in HBM
+before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints ONE JSON line. ``value`` = cell-stage updates per second (cells x 3 x
+steps / wall time) in FP64. The FP32 form of the same workload is reported in
+``fp32``. ``roofline`` covers the dominant kernel (the fused 2D Euler stage
+kernel), timed with HIP events recorded around each stage launch inside the
+timed region. ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample
+on this host.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+VALUES_PER_CELL_STEP = 104      # 2D Euler: algorithmic values moved per cell and step
+KERNEL_SOURCES = ('paper_2411_11229_amd/csrc/hweno_kernels.hip',
+                  'paper_2411_11229_amd/csrc/hweno_device.h')
+PROFILE_JSON = os.path.join(ROOT, 'profiles', 'stage2d_euler_2048_traffic.json')
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), 'rb').read())
+    return h.hexdigest()
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime already loaded by torch."""
+
+    def __init__(self, n):
+        self.hip = ctypes.CDLL('libamdhip64.so')
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.ev = (ctypes.c_void_p * n)()
+        for i in range(n):
+            h = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(h)) != 0:
+                raise RuntimeError('hipEventCreate failed')
+            self.ev[i] = h
+        self.n = n
+
+    def group(self, k, size=4):
+        """ctypes array view of events [k*size, (k+1)*size)."""
+        arr = (ctypes.c_void_p * size)()
+        for j in range(size):
+            arr[j] = self.ev[k * size + j]
+        return arr
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), self.ev[a], self.ev[b]) != 0:
+            raise RuntimeError('hipEventElapsedTime failed')
+        return float(ms.value)
+
+    def close(self):
+        for i in range(self.n):
+            self.hip.hipEventDestroy(self.ev[i])
+
+
+def time_forward(n, precision, steps, warmup, seed=4000):
+    import torch
+    from paper_2411_11229_amd import hweno, workloads
+    w = workloads.euler2d_quadrants(n, seed=seed)
+    prob = hweno.Problem(**w.problem_kwargs(), precision=precision)
+    s = hweno.Solver(prob)
+    dt_ = prob.dtype
+    U = torch.tensor(w.U, dtype=dt_, device='cuda')
+    V = torch.tensor(w.V, dtype=dt_, device='cuda')
+    W = torch.tensor(w.W, dtype=dt_, device='cuda')
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    T_END = w.t_end
+    for _ in range(warmup):
+        s.step(U, V, W, t, T_END)
+    ev = HipEvents(4 * steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.step(U, V, W, t, T_END, events=ev.group(k))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = [[ev.elapsed_ms(4 * k + j, 4 * k + j + 1) for j in range(3)] for k in range(steps)]
+    ev.close()
+    s.health()
+    sim_t = float(t.item())
+    cells = n * n
+    flat = [x for row in stage_ms for x in row]
+    avg_stage = sum(flat) / len(flat)
+    esize = 8 if precision == 'f64' else 4
+    bytes_per_launch = VALUES_PER_CELL_STEP / 3.0 * esize * cells
+    return dict(
+        wall=wall, ms_per_step=1e3 * wall / steps, value=cells * 3 * steps / wall,
+        avg_stage_ms=avg_stage, stage_ms_mean=[sum(r[j] for r in stage_ms) / steps for j in range(3)],
+        bytes_per_launch=bytes_per_launch, achieved_gbs=bytes_per_launch / (avg_stage * 1e-3) / 1e9,
+        sim_time=sim_t, state_finite=bool(torch.isfinite(U).all().item()))
+
+
+def cpu_baseline(n=512, steps=2, seed=4000):
+    """The FP64 oracle (unchanged) on a bounded sample: the same four-quadrant
+    generator at n x n, `steps` SSP-RK3 steps, one thread."""
+    from oracle import hweno as O
+    from paper_2411_11229_amd import workloads
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    w = workloads.euler2d_quadrants(n, seed=seed)
+    p = O.Problem(**w.problem_kwargs())
+    t0 = time.perf_counter()
+    O.run(p, w.U, w.V, w.W, w.t_end, max_steps=steps)
+    el = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, 'unregister') else None
+    return dict(value=n * n * 3 * steps / el, unit='cell-stage updates/s', cores=1,
+                kind='oracle', sample=f'2D Euler four-quadrant {n}x{n}, {steps} SSP-RK3 steps, '
+                                      f'NumPy FP64, 1 thread ({el:.1f} s)')
+
+
+def traffic_record():
+    """HBM bytes per stage launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel sources."""
+    if not os.path.exists(PROFILE_JSON):
+        return None
+    try:
+        rec = json.load(open(PROFILE_JSON))
+    except ValueError:
+        return None
+    if rec.get('kernel_source_sha256') != kernel_hash():
+        return None
+    return rec.get('traffic_bytes_per_launch')
+
+
+def copy_probe(gib=1.0, reps=10):
+    """Plain device copy of known size (for rocprofv3 counter calibration)."""
+    import torch
+    n = int(gib * (1 << 30) // 8)
+    a = torch.ones(n, dtype=torch.float64, device='cuda')
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({'probe': 'copy', 'bytes_read_per_dispatch': n * 8,
+                      'bytes_written_per_dispatch': n * 8, 'reps': reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=30)
+    ap.add_argument('--warmup', type=int, default=5)
+    ap.add_argument('--n', type=int, default=2048)
+    ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle baseline')
+    ap.add_argument('--no-fp32', action='store_true', help='skip the FP32 form')
+    ap.add_argument('--probe', choices=['copy'], help='run a calibration probe instead')
+    ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
+                    help='precision of the headline run')
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f'bench.py: this build measures one GPU only (got --gpus {args.gpus}); '
+              'multi-GPU runs are not part of it.', file=sys.stderr)
+        sys.exit(2)
+    if args.probe == 'copy':
+        copy_probe()
+        return
+
+    import torch
+    if not torch.cuda.is_available():
+        print('bench.py: no HIP device visible', file=sys.stderr)
+        sys.exit(1)
+
+    main_run = time_forward(args.n, args.precision, args.steps, args.warmup)
+    fp32 = None
+    if not args.no_fp32 and args.precision == 'f64':
+        r = time_forward(args.n, 'f32', args.steps, args.warmup)
+        fp32 = dict(value=r['value'], ms_per_step=r['ms_per_step'],
+                    avg_stage_kernel_ms=r['avg_stage_ms'], achieved_gbs=r['achieved_gbs'],
+                    frac=r['achieved_gbs'] / HBM_PEAK_GBS)
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    traffic = traffic_record()
+    roof = dict(bound='hbm', achieved=main_run['achieved_gbs'], peak=HBM_PEAK_GBS, unit='GB/s',
+                frac=main_run['achieved_gbs'] / HBM_PEAK_GBS,
+                traffic=traffic,
+                kernel=f'stage2d_kernel<Euler<2>, {"double" if args.precision == "f64" else "float"}>',
+                algorithmic_bytes_per_launch=main_run['bytes_per_launch'],
+                avg_launch_ms=main_run['avg_stage_ms'],
+                stage_launch_ms=main_run['stage_ms_mean'])
+    out = {
+        'metric': '2D Euler cell-updates/s per RK stage',
+        'value': main_run['value'],
+        'unit': 'cell-stage updates/s',
+        'n_gpus': 1,
+        'steps': args.steps,
+        'warmup': args.warmup,
+        'ms_per_step': main_run['ms_per_step'],
+        'higher_is_better': True,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': args.precision,
+        'data': 'synthetic',
+        'config': {'workload': f'2D Euler {args.n}x{args.n} four-quadrant Riemann, transmissive, '
+                               'production dt (CFL 0.6), seed 4000',
+                   'cells': args.n * args.n, 'gas_gamma': 1.4, 'gamma0': 0.99, 'd0': 0.9,
+                   'eps': 1e-10},
+        'roofline': roof,
+        'cpu_baseline': cpu,
+        'fp32': fp32,
+        'sim_time_reached': main_run['sim_time'],
+        'state_finite': main_run['state_finite'],
+    }
+    print(json.dumps(out))
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,177 @@
+/*
+ * hweno.h -- C ABI of the MI355X (gfx950) implementation of the fifth-order
+ * finite-difference interpolation-based Hermite WENO scheme HWENO-I
+ * (Xie, Tao, Jiao, Zhang, arXiv 2411.11229).
+ *
+ * The library computes, on the GPU:
+ *   - the semi-discrete operator L = (L^1, L^2[, L^3]) of (odeH) / (ode2H) and
+ *     the modified derivatives v~ [, w~] of (limiter), for one stage state;
+ *   - one SSP-RK3 time step of (fully-hweno) / (2Dfully-hweno);
+ *   - the transpose of the Jacobian of that time step (discrete adjoint) at
+ *     the step's recorded Lax-Friedrichs alphas and time step.
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless marked "host".
+ *   - Arrays are structure-of-arrays: [ncomp][ny][nx], x fastest, contiguous,
+ *     element type given by hweno_problem.precision (double or float).
+ *     ncomp = 1 (scalar laws), 3 (1D Euler: rho, rho*u, E),
+ *     4 (2D Euler: rho, rho*u, rho*v, E). In 1D, ny = 1 and every w / W
+ *     argument must be NULL.
+ *   - u is the solution, v = u_x and w = u_y its derivatives (EQ1)/(EQ3); the
+ *     caller supplies all of them.
+ *   - The caller owns every buffer, including the workspace ws, whose size
+ *     comes from hweno_workspace_bytes and which must be passed through
+ *     hweno_workspace_init once before first use. The library allocates no
+ *     device memory and keeps no global state. Calls on different streams
+ *     with different workspaces are independent; calls sharing a workspace
+ *     must be ordered on one stream.
+ *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
+ *     nothing blocks the host except hweno_health.
+ *   - Errors are reported by status code only. Argument errors return
+ *     HWENO_EINVAL before anything is enqueued. Non-finite or non-physical
+ *     states found while reducing wave speeds set sticky flags in the
+ *     workspace, read by hweno_health.
+ */
+#ifndef HWENO_H
+#define HWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HWENO_OK = 0,
+  HWENO_EINVAL = -1,         /* bad argument: null pointer, size, enum, aliasing */
+  HWENO_EUNSUPPORTED = -2,   /* valid but not implemented combination           */
+  HWENO_EDEVICE = -3,        /* a HIP runtime call failed                        */
+  HWENO_ENONFINITE = -4,     /* a NaN / Inf was seen in a state                  */
+  HWENO_ENONPHYSICAL = -5    /* density or pressure <= 0 was seen (Euler)        */
+} hweno_status;
+
+typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_system;
+typedef enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1 } hweno_bc;
+typedef enum { HWENO_F64 = 0, HWENO_F32 = 1 } hweno_precision;
+typedef enum {
+  HWENO_DT_PRODUCTION = 0,   /* dt = cfl / (ax/dx + ay/dy)                    */
+  HWENO_DT_ACCURACY = 1,     /* dt = cfl / (ax/dx^(5/3) + ay/dy^(5/3))        */
+  HWENO_DT_FIXED = 2         /* dt = dt_fixed                                  */
+} hweno_dt_rule;
+
+/*
+ * The problem, following the paper's statement: a uniform cell-centred mesh
+ * (section 2: x_i, dx; section 3: y_j, dy), the flux (scalar advection
+ * f = a u, g = b u; Burgers f = g = u^2/2; Euler (euler1d)/(euler2d) with
+ * E = P/(gas_gamma - 1) + rho |vel|^2 / 2), the linear weights of (interp)
+ * (gamma0; gamma1 = gamma2 = (1 - gamma0)/2) and of (limiter) (d0;
+ * d1 = d2 = (1 - d0)/2), and epsilon of (nonlinear). The paper uses
+ * gamma0 = 0.95 (1D) / 0.99 (2D), d0 = 0.9, eps = 1e-10.
+ */
+typedef struct {
+  int32_t dim;          /* 1 or 2                                                */
+  int32_t nx, ny;       /* cells; nx >= 5; ny >= 5 in 2D, ny == 1 in 1D           */
+  double dx, dy;        /* > 0; dy ignored in 1D                                  */
+  int32_t system;       /* hweno_system                                           */
+  double adv_a, adv_b;  /* advection speeds (HWENO_ADVECTION only)                */
+  double gas_gamma;     /* ratio of specific heats, > 1 (HWENO_EULER only)        */
+  double gamma0;        /* in (0, 1)                                              */
+  double d0;            /* in (0, 1)                                              */
+  double eps;           /* > 0                                                    */
+  int32_t bc[4];        /* hweno_bc at x_lo, x_hi, y_lo, y_hi. Periodic must be  */
+                        /* set on both ends of an axis. Transmissive copies the  */
+                        /* nearest interior u, v, w into the 2 ghost cells.      */
+  int32_t precision;    /* hweno_precision of every array argument                */
+} hweno_problem;
+
+/* Human-readable name of a status code (static string). */
+const char* hweno_status_string(hweno_status s);
+
+/* Validates `prob` (host) and stores the workspace size in bytes (host). */
+hweno_status hweno_workspace_bytes(const hweno_problem* prob, size_t* bytes);
+
+/* Clears the workspace's flag word and scalars. Call once per workspace
+ * before its first use (enqueued on `stream`). */
+hweno_status hweno_workspace_init(const hweno_problem* prob, void* ws, hipStream_t stream);
+
+/*
+ * Lax-Friedrichs alphas of (flux-LF): alpha[0] = max over interior cells of
+ * |f'(u)| (Euler: |u| + c), alpha[1] the same for g (0 in 1D).
+ * u: [ncomp][ny][nx]; alpha: device double[2], written.
+ */
+hweno_status hweno_max_wavespeed(const hweno_problem* prob, const void* u, double* alpha,
+                                 void* ws, hipStream_t stream);
+
+/*
+ * One evaluation of the spatial operator, Steps 1-4 of sections 2 and 3:
+ * Lu, Lv, Lw <- L^1, L^2, L^3 of (odeH)/(ode2H) at the state (u, v, w) with
+ * the given alphas (device double[2]); vtilde, wtilde <- the modified
+ * derivatives of (limiter) in x and y. For systems the interpolation and
+ * the limiter run in local characteristic variables of the cell centre.
+ * Outputs must not alias inputs. In 1D, w, Lw and wtilde are NULL.
+ */
+hweno_status hweno_rhs(const hweno_problem* prob, const void* u, const void* v, const void* w,
+                       const double* alpha, void* Lu, void* Lv, void* Lw,
+                       void* vtilde, void* wtilde, void* ws, hipStream_t stream);
+
+/*
+ * One SSP-RK3 step (fully-hweno)/(2Dfully-hweno), in place on (u, v, w).
+ * Each stage takes its alphas from its own state (stage 1 from (u, v, w)).
+ * dt from dt_rule (hweno_dt_rule) with `cfl`, or dt_fixed, from the stage-1
+ * alphas, then clipped so that *t + dt does not pass t_end; when *t >= t_end
+ * on entry the step leaves every buffer untouched.
+ *   t          device double, in/out: advanced by dt (set to t_end on the
+ *              clipped last step).
+ *   dt_used    device double, out (may be NULL): the dt taken (0 if skipped).
+ *   alpha_rec  device double[3][2], out (may be NULL): the alphas of the
+ *              three stages, as needed by hweno_adjoint_step.
+ *   stages     device buffer of 2 * 3 * ncomp planes (2D; 2 * 2 * ncomp in
+ *              1D) of the array type, out (may be NULL): the stage states
+ *              X^(1), X^(2) as [stage][field u,v,w][comp][ny][nx].
+ */
+hweno_status hweno_step(const hweno_problem* prob, void* u, void* v, void* w,
+                        int32_t dt_rule, double cfl, double dt_fixed, double t_end,
+                        double* t, double* dt_used, double* alpha_rec, void* stages,
+                        void* ws, hipStream_t stream);
+
+/*
+ * hweno_step with instrumentation for timing: `events` (host array of 4
+ * hipEvent_t created by the caller, or NULL) are recorded on `stream` right
+ * before the stage-1 launch, after stage 1, after stage 2 and after stage 3,
+ * so the elapsed times between consecutive events are the durations of the
+ * three stage kernels. Arguments and results are otherwise those of
+ * hweno_step.
+ */
+hweno_status hweno_step_profiled(const hweno_problem* prob, void* u, void* v, void* w,
+                                 int32_t dt_rule, double cfl, double dt_fixed, double t_end,
+                                 double* t, double* dt_used, double* alpha_rec, void* stages,
+                                 void* ws, hipStream_t stream, hipEvent_t* events);
+
+/*
+ * Discrete adjoint of one hweno_step (row a12 of the design: derived from
+ * (fully-hweno)/(2Dfully-hweno)). Given lambda = dJ/dX^{n+1} (lam_*_in) it
+ * writes dJ/dX^n (lam_*_out), where X = (u, v, w), with the recorded dt
+ * (device double) and stage alphas (device double[3][2]) held fixed, i.e.
+ * not differentiated. (u_n, v_n, w_n) is the step's initial state. `stages`
+ * holds X^(1), X^(2) as written by hweno_step, or is NULL, in which case
+ * they are recomputed. At the kinks of |beta0 - beta_k| the derivative of
+ * |.| is taken as sign(0) = 0. Output buffers must not alias any input.
+ */
+hweno_status hweno_adjoint_step(const hweno_problem* prob, const void* u_n, const void* v_n,
+                                const void* w_n, const void* stages, const double* dt,
+                                const double* alpha_rec, const void* lam_u_in,
+                                const void* lam_v_in, const void* lam_w_in, void* lam_u_out,
+                                void* lam_v_out, void* lam_w_out, void* ws, hipStream_t stream);
+
+/* Synchronises `stream` and reports the sticky state flags of `ws`:
+ * HWENO_ENONFINITE, HWENO_ENONPHYSICAL or HWENO_OK. clear != 0 resets them. */
+hweno_status hweno_health(const hweno_problem* prob, void* ws, hipStream_t stream, int32_t clear);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWENO_H */

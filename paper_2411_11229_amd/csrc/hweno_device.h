@@ -1,0 +1,405 @@
+// Device math of the HWENO-I scheme for gfx950 (Xie, Tao, Jiao, Zhang,
+// arXiv 2411.11229). Everything here is per point or per lane; the kernels in
+// hweno_kernels.hip arrange it into marching stencil sweeps.
+//
+// Type conventions: T is the storage / streaming type (double or float).
+// The smoothness indicators, tau, epsilon and the nonlinear-weight ratios are
+// always evaluated in double, as are the flux differences and the Runge-Kutta
+// combination (done by the kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hweno {
+
+constexpr int kWave = 64;                 // lanes per wavefront (CDNA)
+constexpr int kHalo = 2;                  // stencil radius: x_{i+1/2} reads cells i-1..i+2
+constexpr int kXOut = kWave - 2 * kHalo;  // output columns per wavefront
+
+// Scheme constants as the kernels need them.
+struct Scheme {
+  double dx, dy, idx, idy;  // mesh widths and their inverses
+  double gamma0, g1;        // linear weights of (interp); g1 = gamma1 = gamma2
+  double d0, d1;            // linear weights of (limiter); d1 = d1 = d2
+  double eps;               // epsilon of (nonlinear)
+  double gas;               // ratio of specific heats (Euler)
+  double adv_a, adv_b;      // advection speeds
+};
+
+// ---------------------------------------------------------------- lane shifts
+// Values of the neighbouring lane along x (lanes are consecutive cells).
+template <typename T>
+__device__ __forceinline__ T from_prev(T x) { return __shfl_up(x, 1); }
+template <typename T>
+__device__ __forceinline__ T from_next(T x) { return __shfl_down(x, 1); }
+
+// ---------------------------------------------------------------- HWENO-I
+// One HWENO-I application on one scalar line (a conserved component for the
+// scalar laws, a characteristic variable for systems), section 2.1:
+// from u_{i-1}, u_i, u_{i+1}, v_{i-1}, v_{i+1} it returns
+//   uR = u^-_{i+1/2} and uL = u^+_{i-1/2}  -- (interp) and its mirror image,
+//   vt = the modified derivative at x_i    -- (limiter),
+// sharing one set of smoothness indicators (GHYZ) between the three.
+//
+// With the normalised weights w_l = lin_l (1 + r_l) / S, r_l = tau/(beta_l +
+// eps), the combination of (interp) is rewritten as
+//   [ (1+r0) (p0 - g1 (p1 + p2)) + g1 ((1+r1) p1 + (1+r2) p2) ] / S,
+// which needs gamma1 = gamma2 (the paper's choice). The three ratios share
+// one division, and both normalisations share another.
+template <typename T>
+__device__ __forceinline__ void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
+                                            double h, double ih, T& uR, T& uL, T& vt) {
+  const double dm = (double)um, dc = (double)u0, dp = (double)up;
+  const double sv = 0.25 * h * ((double)vm + (double)vp);
+  const double dv = 0.25 * h * ((double)vm - (double)vp);
+  const double cdf = dp - dm;                 // u_{i+1} - u_{i-1}
+  const double sdf = dm - 2.0 * dc + dp;      // u_{i-1} - 2u_i + u_{i+1}
+  // (GHYZ) closed form: a1..a4 and beta0; beta1, beta2
+  const double a1 = 0.75 * cdf - sv;
+  const double a2 = sdf + dv;
+  const double a3 = sv - 0.25 * cdf;
+  const double a4 = -0.5 * sdf - dv;
+  const double t1 = a1 + 0.25 * a3;
+  const double t2 = a2 + (63.0 / 130.0) * a4;
+  const double b0 = t1 * t1 + (13.0 / 3.0) * t2 * t2 + (781.0 / 20.0) * a3 * a3 +
+                    (1421461.0 / 2275.0) * a4 * a4;
+  const double e1 = dc - dm, e2 = dp - dc;
+  const double b1 = e1 * e1, b2 = e2 * e2;
+  // (nonlinear)
+  const double ts = fabs(b0 - b1) + fabs(b0 - b2);
+  const double tau = 0.25 * ts * ts;
+  const double q0 = b0 + s.eps, q1 = b1 + s.eps, q2 = b2 + s.eps;
+  const double q12 = q1 * q2;
+  const double ti = tau / (q0 * q12);
+  const double o0 = 1.0 + ti * q12;           // 1 + tau/(beta0+eps)
+  const double o1 = 1.0 + ti * (q0 * q2);     // 1 + tau/(beta1+eps)
+  const double o2 = 1.0 + ti * (q0 * q1);     // 1 + tau/(beta2+eps)
+  const double Sg = s.gamma0 * o0 + s.g1 * (o1 + o2);
+  const double Sd = s.d0 * o0 + s.d1 * (o1 + o2);
+  const double inv = 1.0 / (Sg * Sd);
+  const double iSg = Sd * inv, iSd = Sg * inv;
+  // (Pxi): candidates at x_{i+1/2}
+  const double vmd = (double)vm, vpd = (double)vp;
+  const double P0 = -0.125 * dm + 0.5625 * (dc + dp) - h * (0.046875 * vmd + 0.140625 * vpd);
+  const double P1 = -0.5 * dm + 1.5 * dc;
+  const double P2 = 0.5 * (dc + dp);
+  // mirror image: candidates at x_{i-1/2}; Q1 lives on {i, i+1}, Q2 on {i-1, i}
+  const double Q0 = -0.125 * dp + 0.5625 * (dc + dm) + h * (0.046875 * vpd + 0.140625 * vmd);
+  const double Q1 = -0.5 * dp + 1.5 * dc;
+  const double Q2 = 0.5 * (dc + dm);
+  // (limiter-p): candidate derivatives at x_i
+  const double D0 = 0.75 * ih * cdf - 0.25 * (vmd + vpd);
+  const double D1 = ih * e1;
+  const double D2 = ih * e2;
+  uR = (T)((o0 * (P0 - s.g1 * (P1 + P2)) + s.g1 * (o1 * P1 + o2 * P2)) * iSg);
+  uL = (T)((o0 * (Q0 - s.g1 * (Q1 + Q2)) + s.g1 * (o2 * Q1 + o1 * Q2)) * iSg);
+  vt = (T)((o0 * (D0 - s.d1 * (D1 + D2)) + s.d1 * (o1 * D1 + o2 * D2)) * iSd);
+}
+
+// (P'xi) and its mirror: v^-_{i+1/2} = p0'(x_{i+1/2}), v^+_{i-1/2} = p0'(x_{i-1/2}).
+// Linear in the data, hence the same in conserved or characteristic variables.
+template <typename T>
+__device__ __forceinline__ void face_derivs(T um, T u0, T up, T vm, T vp, T ih, T& vR, T& vL) {
+  vR = (T(0.1875) * um - T(1.5) * u0 + T(1.3125) * up) * ih + T(0.0625) * vm - T(0.1875) * vp;
+  vL = (T(-1.3125) * um + T(1.5) * u0 - T(0.1875) * up) * ih - T(0.1875) * vm + T(0.0625) * vp;
+}
+
+// (Cd-1)-(DfDh), with the coefficients of each combination collected:
+//   D(f) = -97/1920 (f_{i-1} - f_i - f_{i+1} + f_{i+2}) - 19/960 dx (h_{i-1} - h_{i+2})
+//   D(h) = [697/5184 (f_{i-1} - f_{i+2}) - 61/192 (f_i - f_{i+1})] / dx
+//          + 37/864 (h_{i-1} + h_{i+2})
+template <typename T>
+__device__ __forceinline__ void central_corr(T fm1, T f0, T fp1, T fp2, T hm1, T hp2, T h, T ih,
+                                             T& Df, T& Dh) {
+  const T s4 = (fm1 + fp2) - (f0 + fp1);
+  Df = T(-97.0 / 1920.0) * s4 - T(19.0 / 960.0) * h * (hm1 - hp2);
+  Dh = (T(697.0 / 5184.0) * (fm1 - fp2) - T(61.0 / 192.0) * (f0 - fp1)) * ih +
+       T(37.0 / 864.0) * (hm1 + hp2);
+}
+
+// (mixed): interface value of a mixed-derivative flux.
+template <typename T>
+__device__ __forceinline__ T mixed_face(T em1, T e0, T ep1, T ep2) {
+  return (T(7.0) * (e0 + ep1) - (em1 + ep2)) * T(1.0 / 12.0);
+}
+
+// ---------------------------------------------------------------- systems
+// Each system provides, for direction D (0 = x, 1 = y):
+//   prim(U)                      per-point quantities shared by the rest
+//   flux<D>(U, pr, F)            f or g
+//   jac<D>(U, pr, V, out)        f'(U) V (the fluxes h, eta, xi, theta)
+//   eig<D>(U, pr) / left / right characteristic basis (systems only)
+//   speed<D>(U)                  spectral radius for the LF alpha
+//   admissible(U)                finite, and rho > 0, p > 0 for Euler
+struct Advection {
+  static constexpr int NC = 1;
+  static constexpr bool kChar = false;
+  double a, b;
+  template <typename T> struct Prim {};
+  template <typename T>
+  __device__ __forceinline__ Prim<T> prim(const T (&)[NC]) const { return {}; }
+  template <int D, typename T>
+  __device__ __forceinline__ void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
+    F[0] = T(D == 0 ? a : b) * U[0];
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ void jac(const T (&)[NC], const Prim<T>&, const T (&V)[NC],
+                                      T (&O)[NC]) const {
+    O[0] = T(D == 0 ? a : b) * V[0];
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ double speed(const T (&)[NC]) const { return fabs(D == 0 ? a : b); }
+  template <typename T>
+  __device__ __forceinline__ unsigned admissible(const T (&U)[NC]) const {
+    return isfinite((double)U[0]) ? 0u : 1u;
+  }
+};
+
+struct Burgers {
+  static constexpr int NC = 1;
+  static constexpr bool kChar = false;
+  template <typename T> struct Prim {};
+  template <typename T>
+  __device__ __forceinline__ Prim<T> prim(const T (&)[NC]) const { return {}; }
+  template <int D, typename T>
+  __device__ __forceinline__ void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
+    F[0] = T(0.5) * U[0] * U[0];
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ void jac(const T (&U)[NC], const Prim<T>&, const T (&V)[NC],
+                                      T (&O)[NC]) const {
+    O[0] = U[0] * V[0];
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ double speed(const T (&U)[NC]) const { return fabs((double)U[0]); }
+  template <typename T>
+  __device__ __forceinline__ unsigned admissible(const T (&U)[NC]) const {
+    return isfinite((double)U[0]) ? 0u : 1u;
+  }
+};
+
+// Euler equations (euler1d) / (euler2d), U = (rho, rho u[, rho v], E),
+// P = (gas - 1) (E - rho |vel|^2 / 2).
+template <int DIM>
+struct Euler {
+  static constexpr int NC = DIM + 2;
+  static constexpr bool kChar = true;
+  static constexpr int E_ = NC - 1;
+  double gas;
+
+  template <typename T>
+  struct Prim {
+    T ir, mu, nu, k, p, Ep;  // 1/rho, u, v, |vel|^2/2, P, E + P
+  };
+  template <typename T>
+  __device__ __forceinline__ Prim<T> prim(const T (&U)[NC]) const {
+    Prim<T> q;
+    q.ir = T(1) / U[0];
+    q.mu = U[1] * q.ir;
+    q.nu = DIM == 2 ? U[2] * q.ir : T(0);
+    q.k = T(0.5) * (q.mu * q.mu + q.nu * q.nu);
+    q.p = T(gas - 1.0) * (U[E_] - U[0] * q.k);
+    q.Ep = U[E_] + q.p;
+    return q;
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ void flux(const T (&U)[NC], const Prim<T>& q, T (&F)[NC]) const {
+    if constexpr (DIM == 1) {
+      F[0] = U[1];
+      F[1] = U[1] * q.mu + q.p;
+      F[2] = q.mu * q.Ep;
+    } else if constexpr (D == 0) {
+      F[0] = U[1];
+      F[1] = U[1] * q.mu + q.p;
+      F[2] = U[1] * q.nu;
+      F[3] = q.mu * q.Ep;
+    } else {
+      F[0] = U[2];
+      F[1] = U[2] * q.mu;
+      F[2] = U[2] * q.nu + q.p;
+      F[3] = q.nu * q.Ep;
+    }
+  }
+  // A(U) V by the chain rule through the primitives: with d(.) the derivative
+  // along V, du = (V1 - u V0)/rho, dv = (V2 - v V0)/rho and
+  // dP = (gas-1)(V_E - u V1 - v V2 + k V0).
+  template <int D, typename T>
+  __device__ __forceinline__ void jac(const T (&U)[NC], const Prim<T>& q, const T (&V)[NC],
+                                      T (&O)[NC]) const {
+    const T gm1 = T(gas - 1.0);
+    if constexpr (DIM == 1) {
+      const T du = (V[1] - q.mu * V[0]) * q.ir;
+      const T dP = gm1 * (V[2] - q.mu * V[1] + q.k * V[0]);
+      O[0] = V[1];
+      O[1] = q.mu * V[1] + U[1] * du + dP;
+      O[2] = du * q.Ep + q.mu * (V[2] + dP);
+    } else {
+      const T du = (V[1] - q.mu * V[0]) * q.ir;
+      const T dv = (V[2] - q.nu * V[0]) * q.ir;
+      const T dP = gm1 * (V[3] - q.mu * V[1] - q.nu * V[2] + q.k * V[0]);
+      if constexpr (D == 0) {
+        O[0] = V[1];
+        O[1] = q.mu * V[1] + U[1] * du + dP;
+        O[2] = q.nu * V[1] + U[1] * dv;
+        O[3] = du * q.Ep + q.mu * (V[3] + dP);
+      } else {
+        O[0] = V[2];
+        O[1] = q.mu * V[2] + U[2] * du;
+        O[2] = q.nu * V[2] + U[2] * dv + dP;
+        O[3] = dv * q.Ep + q.nu * (V[3] + dP);
+      }
+    }
+  }
+
+  // Characteristic basis of A_D(U) at a cell centre: rows of L and columns
+  // of R for the eigenvalues (vel-c, vel, [vel,] vel+c); R in the textbook
+  // normalisation and L = R^{-1} in closed form (b1 = (gas-1)/c^2,
+  // b2 = b1 k, H = (E+P)/rho).
+  template <typename T>
+  struct Eig {
+    T mu, nu, k, c, ic, H, b1, b2;
+  };
+  template <typename T>
+  __device__ __forceinline__ Eig<T> eig(const Prim<T>& q) const {
+    Eig<T> e;
+    e.mu = q.mu;
+    e.nu = q.nu;
+    e.k = q.k;
+    const T c2 = T(gas) * q.p * q.ir;
+    e.c = sqrt(c2);
+    e.ic = T(1) / e.c;
+    e.H = q.Ep * q.ir;
+    e.b1 = T(gas - 1.0) * e.ic * e.ic;
+    e.b2 = e.b1 * q.k;
+    return e;
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ void left(const Eig<T>& e, int j, T (&l)[NC]) const {
+    const T vn = D == 0 ? e.mu : e.nu;    // normal velocity
+    if constexpr (DIM == 1) {
+      if (j == 0) { l[0] = T(0.5) * (e.b2 + e.mu * e.ic); l[1] = T(-0.5) * (e.b1 * e.mu + e.ic); l[2] = T(0.5) * e.b1; }
+      else if (j == 1) { l[0] = T(1) - e.b2; l[1] = e.b1 * e.mu; l[2] = -e.b1; }
+      else { l[0] = T(0.5) * (e.b2 - e.mu * e.ic); l[1] = T(0.5) * (e.ic - e.b1 * e.mu); l[2] = T(0.5) * e.b1; }
+    } else {
+      if (j == 0) {
+        l[0] = T(0.5) * (e.b2 + vn * e.ic);
+        l[1] = T(-0.5) * (e.b1 * e.mu + (D == 0 ? e.ic : T(0)));
+        l[2] = T(-0.5) * (e.b1 * e.nu + (D == 1 ? e.ic : T(0)));
+        l[3] = T(0.5) * e.b1;
+      } else if (j == 1) {
+        l[0] = T(1) - e.b2; l[1] = e.b1 * e.mu; l[2] = e.b1 * e.nu; l[3] = -e.b1;
+      } else if (j == 2) {
+        if (D == 0) { l[0] = -e.nu; l[1] = T(0); l[2] = T(1); l[3] = T(0); }
+        else { l[0] = -e.mu; l[1] = T(1); l[2] = T(0); l[3] = T(0); }
+      } else {
+        l[0] = T(0.5) * (e.b2 - vn * e.ic);
+        l[1] = T(0.5) * ((D == 0 ? e.ic : T(0)) - e.b1 * e.mu);
+        l[2] = T(0.5) * ((D == 1 ? e.ic : T(0)) - e.b1 * e.nu);
+        l[3] = T(0.5) * e.b1;
+      }
+    }
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ void right(const Eig<T>& e, int j, T (&r)[NC]) const {
+    const T vn = D == 0 ? e.mu : e.nu;
+    if constexpr (DIM == 1) {
+      if (j == 0) { r[0] = T(1); r[1] = e.mu - e.c; r[2] = e.H - e.mu * e.c; }
+      else if (j == 1) { r[0] = T(1); r[1] = e.mu; r[2] = e.k; }
+      else { r[0] = T(1); r[1] = e.mu + e.c; r[2] = e.H + e.mu * e.c; }
+    } else {
+      if (j == 0 || j == 3) {
+        const T sc = j == 0 ? -e.c : e.c;
+        r[0] = T(1);
+        r[1] = e.mu + (D == 0 ? sc : T(0));
+        r[2] = e.nu + (D == 1 ? sc : T(0));
+        r[3] = e.H + vn * sc;
+      } else if (j == 1) {
+        r[0] = T(1); r[1] = e.mu; r[2] = e.nu; r[3] = e.k;
+      } else {
+        if (D == 0) { r[0] = T(0); r[1] = T(0); r[2] = T(1); r[3] = e.nu; }
+        else { r[0] = T(0); r[1] = T(1); r[2] = T(0); r[3] = e.mu; }
+      }
+    }
+  }
+  template <int D, typename T>
+  __device__ __forceinline__ double speed(const T (&U)[NC]) const {
+    const double r = (double)U[0];
+    const double mu = (double)U[1] / r;
+    const double nu = DIM == 2 ? (double)U[2] / r : 0.0;
+    const double p = (gas - 1.0) * ((double)U[E_] - 0.5 * r * (mu * mu + nu * nu));
+    return fabs(D == 0 ? mu : nu) + sqrt(gas * p / r);
+  }
+  template <typename T>
+  __device__ __forceinline__ unsigned admissible(const T (&U)[NC]) const {
+    unsigned f = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) f |= isfinite((double)U[c]) ? 0u : 1u;
+    const double r = (double)U[0];
+    const double mu = (double)U[1] / r;
+    const double nu = DIM == 2 ? (double)U[2] / r : 0.0;
+    const double p = (gas - 1.0) * ((double)U[E_] - 0.5 * r * (mu * mu + nu * nu));
+    if (!(r > 0.0) || !(p > 0.0)) f |= 2u;
+    return f;
+  }
+};
+
+// HWENO-I on one cell for a system, in direction D: project the stencil on
+// the characteristic basis of the cell centre, apply hweno_point to every
+// characteristic variable, project back (remarks on local characteristic
+// decomposition in sections 2 and 3). Scalar laws skip the projection.
+template <int D, class Sys, typename T>
+__device__ __forceinline__ void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
+                                           const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
+                                           const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
+                                           const T (&Ap)[Sys::NC], T (&uR)[Sys::NC],
+                                           T (&uL)[Sys::NC], T (&at)[Sys::NC]) {
+  constexpr int NC = Sys::NC;
+  if constexpr (!Sys::kChar) {
+    hweno_point<T>(Um[0], U0[0], Up[0], Am[0], Ap[0], s, h, ih, uR[0], uL[0], at[0]);
+  } else {
+    const auto q = sy.prim(U0);
+    const auto e = sy.eig(q);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) { uR[c] = T(0); uL[c] = T(0); at[c] = T(0); }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      T l[NC];
+      sy.template left<D>(e, j, l);
+      T wm = T(0), w0 = T(0), wp = T(0), am = T(0), ap = T(0);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        wm += l[c] * Um[c];
+        w0 += l[c] * U0[c];
+        wp += l[c] * Up[c];
+        am += l[c] * Am[c];
+        ap += l[c] * Ap[c];
+      }
+      T cr, cl, ct;
+      hweno_point<T>(wm, w0, wp, am, ap, s, h, ih, cr, cl, ct);
+      T r[NC];
+      sy.template right<D>(e, j, r);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        uR[c] += r[c] * cr;
+        uL[c] += r[c] * cl;
+        at[c] += r[c] * ct;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- index maps
+// Ghost cells by index map: periodic wraps, transmissive clamps (copies the
+// nearest interior cell). Any integer i is accepted.
+__device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
+  if (i >= 0 && i < n) return i;
+  const int side = i < 0 ? lo : hi;
+  if (side == 0) {
+    int m = i % n;
+    return m < 0 ? m + n : m;
+  }
+  return i < 0 ? 0 : n - 1;
+}
+
+}  // namespace hweno

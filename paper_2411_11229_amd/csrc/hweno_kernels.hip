@@ -1,0 +1,848 @@
+// HIP kernels and C ABI of the HWENO-I hot path for gfx950.
+//
+// Forward stage kernel ("marcher"): one wavefront per block. The 64 lanes
+// hold 64 consecutive cells of a row (60 output columns plus a 2-cell halo
+// on each side); x-neighbours are read across lanes. The wavefront marches
+// up a strip of rows, keeping in registers the rows the y-stencil still
+// needs, so every cell's HWENO interpolation is done once per direction and
+// every input value is read from memory once per strip (plus halos).
+// Per output cell and stage it does: the x-sweep (HWENO, pointwise fluxes,
+// central correction, LF flux, mixed flux, flux difference), the y-sweep
+// likewise, the residual (odeH)/(ode2H) and the SSP-RK3 combination
+// (fully-hweno)/(2Dfully-hweno), and, for stages 1-2, the max wave speed of
+// the new state for the next stage's Lax-Friedrichs alpha.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <type_traits>
+
+#include "../../include/hweno.h"
+#include "hweno_device.h"
+
+namespace hweno {
+
+enum Mode { kRhs = 0, kStage1 = 1, kStage2 = 2, kStage3 = 3 };
+
+template <typename T>
+struct StageArgs {
+  const T* U;  const T* V;  const T* W;   // stage state X (W null in 1D)
+  const T* Ub; const T* Vb; const T* Wb;  // RK base B^n = (U^n, V~^n, W~^n), stages 2-3
+  T* Uo; T* Vo; T* Wo;                    // new state (stages) or L^1..L^3 (rhs)
+  T* Vt; T* Wt;                           // stage 1: V~^n, W~^n; rhs: modified derivatives
+  const double* alpha;                    // [2] LF alphas of this stage
+  const double* dt;                       // stages: time step
+  const int* active;                      // stages: 0 = the step is skipped
+  unsigned long long* alpha_next;         // [2] atomic max of the new state's speeds, or null
+  unsigned* flags;                        // sticky state flags, or null
+  double* alpha_rec;                      // [2] record of the alphas used, or null
+  int nx, ny, rows;                       // rows: output rows per block (2D)
+  int plane;                              // nx * ny
+  int bc[4];
+  Scheme s;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T from_next2(T x) { return __shfl_down(x, 2); }
+
+// Atomic max of non-negative doubles through their bit patterns (ordered
+// like unsigned integers); order-independent, hence deterministic.
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) {
+  atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+// ------------------------------------------------------ x-direction sweep
+// Steps 1-4 of section 2 along x for the row held by the wavefront (one cell
+// per lane). Inputs: this lane's U, V (= u_x) and, with NF == 3, W (= u_y).
+// Outputs: residual parts -(F_{i+1/2} - F_{i-1/2})/dx of the u-, v- and
+// w-equations (the last from the mixed flux eta = f'(u) w), accumulated in
+// double, and the modified derivative v~. Valid on lanes 2..61.
+template <int NF, class Sys, typename T>
+__device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, double alpha,
+                                        const T (&U)[Sys::NC], const T (&V)[Sys::NC],
+                                        const T (&W)[Sys::NC], double (&RU)[Sys::NC],
+                                        double (&RV)[Sys::NC], double (&RW)[Sys::NC],
+                                        T (&vt)[Sys::NC]) {
+  constexpr int NC = Sys::NC;
+  const T h = T(s.dx), ih = T(s.idx);
+  T Um[NC], Up[NC], Vm[NC], Vp[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    Um[c] = from_prev(U[c]);
+    Up[c] = from_next(U[c]);
+    Vm[c] = from_prev(V[c]);
+    Vp[c] = from_next(V[c]);
+  }
+  // Step 1: HWENO once per cell -> u at both faces, v~ at the centre
+  T uR[NC], uL[NC], vR[NC], vL[NC];
+  hweno_cell<0>(sy, s, s.dx, s.idx, Um, U, Up, Vm, Vp, uR, uL, vt);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Vm[c], Vp[c], ih, vR[c], vL[c]);
+  // pointwise f, h = f'(u) v, eta = f'(u) w at the cell centre
+  T f[NC], hf[NC], e[NC];
+  {
+    const auto q = sy.prim(U);
+    sy.template flux<0>(U, q, f);
+    sy.template jac<0>(U, q, V, hf);
+    if constexpr (NF == 3) sy.template jac<0>(U, q, W, e);
+  }
+  // Lax-Friedrichs halves of this cell's faces (flux-LF): the minus side of
+  // x_{i+1/2} and the plus side of x_{i-1/2}
+  T mF[NC], mH[NC], pF[NC], pH[NC];
+  {
+    const T a = T(alpha);
+    T fr[NC], hr[NC], fl[NC], hl[NC];
+    const auto qr = sy.prim(uR);
+    sy.template flux<0>(uR, qr, fr);
+    sy.template jac<0>(uR, qr, vR, hr);
+    const auto ql = sy.prim(uL);
+    sy.template flux<0>(uL, ql, fl);
+    sy.template jac<0>(uL, ql, vL, hl);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      mF[c] = T(0.5) * (fr[c] + a * uR[c]);
+      mH[c] = T(0.5) * (hr[c] + a * vR[c]);
+      pF[c] = T(0.5) * (fl[c] - a * uL[c]);
+      pH[c] = T(0.5) * (hl[c] - a * vL[c]);
+    }
+  }
+  // Steps 2-3 at x_{i+1/2}, then Step 4
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const T fm1 = from_prev(f[c]), fp1 = from_next(f[c]), fp2 = from_next2(f[c]);
+    const T hm1 = from_prev(hf[c]), hp2 = from_next2(hf[c]);
+    T Df, Dh;
+    central_corr(fm1, f[c], fp1, fp2, hm1, hp2, h, ih, Df, Dh);
+    const T Fi = mF[c] + from_next(pF[c]) + Df;
+    const T Hi = mH[c] + from_next(pH[c]) + Dh;
+    RU[c] = -((double)Fi - (double)from_prev(Fi)) * s.idx;
+    RV[c] = -((double)Hi - (double)from_prev(Hi)) * s.idx;
+    if constexpr (NF == 3) {
+      const T Ei = mixed_face(from_prev(e[c]), e[c], from_next(e[c]), from_next2(e[c]));
+      RW[c] = -((double)Ei - (double)from_prev(Ei)) * s.idx;
+    }
+  }
+}
+
+// RK combination of one output cell (all in double, one rounding at store).
+template <int MODE>
+__device__ __forceinline__ double rk(double x, double base, double dt, double L) {
+  if constexpr (MODE == kStage1) return x + dt * L;
+  else if constexpr (MODE == kStage2) return 0.75 * base + 0.25 * (x + dt * L);
+  else if constexpr (MODE == kStage3) return base / 3.0 + (2.0 / 3.0) * (x + dt * L);
+  else return L;
+}
+
+// ------------------------------------------------------------ 1D stage kernel
+template <class Sys, typename T, int MODE>
+__global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
+  constexpr int NC = Sys::NC;
+  if (MODE != kRhs && A.active && *A.active == 0) return;
+  const int lane = threadIdx.x;
+  const int col = blockIdx.x * kXOut - kHalo + lane;
+  const int g = map_index(col, A.nx, A.bc[0], A.bc[1]);
+  const bool out = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
+  const double ax = A.alpha[0];
+  const double dt = MODE == kRhs ? 0.0 : *A.dt;
+  if (MODE != kRhs && A.alpha_rec && blockIdx.x == 0 && lane == 0) {
+    A.alpha_rec[0] = ax;
+    A.alpha_rec[1] = 0.0;
+  }
+  T U[NC], V[NC], W[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    U[c] = A.U[c * A.plane + g];
+    V[c] = A.V[c * A.plane + g];
+  }
+  double RU[NC], RV[NC], RW[NC];
+  T vt[NC];
+  sweep_x<2>(sy, A.s, ax, U, V, W, RU, RV, RW, vt);
+  double smax = 0.0;
+  unsigned flag = 0;
+  if (out) {
+    T Un[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int o = c * A.plane + col;
+      const double ub = MODE >= kStage2 ? (double)A.Ub[o] : 0.0;
+      const double vb = MODE >= kStage2 ? (double)A.Vb[o] : 0.0;
+      Un[c] = (T)rk<MODE>((double)U[c], ub, dt, RU[c]);
+      A.Uo[o] = Un[c];
+      A.Vo[o] = (T)rk<MODE>((double)vt[c], vb, dt, RV[c]);
+      if (MODE == kStage1 || MODE == kRhs) A.Vt[o] = vt[c];
+    }
+    if (A.alpha_next) {
+      smax = sy.template speed<0>(Un);
+      flag = sy.admissible(Un);
+    }
+  }
+  if (A.alpha_next) {
+    smax = wave_max(smax);
+    flag = wave_or(flag);
+    if (lane == 0) {
+      atomic_max_pos(A.alpha_next, smax);
+      if (flag && A.flags) atomicOr(A.flags, flag);
+    }
+  }
+}
+
+// ------------------------------------------------------------ 2D stage kernel
+template <class Sys, typename T>
+__device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol,
+                                         T (&U)[Sys::NC], T (&V)[Sys::NC], T (&W)[Sys::NC]) {
+  const int gr = map_index(r, A.ny, A.bc[2], A.bc[3]);
+  const int off = gr * A.nx + gcol;
+#pragma unroll
+  for (int c = 0; c < Sys::NC; ++c) {
+    U[c] = A.U[c * A.plane + off];
+    V[c] = A.V[c * A.plane + off];
+    W[c] = A.W[c * A.plane + off];
+  }
+}
+
+template <class Sys, typename T, int MODE>
+__global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
+  constexpr int NC = Sys::NC;
+  if (MODE != kRhs && A.active && *A.active == 0) return;
+  const Scheme& s = A.s;
+  const int lane = threadIdx.x;
+  const int col = blockIdx.x * kXOut - kHalo + lane;
+  const int gcol = map_index(col, A.nx, A.bc[0], A.bc[1]);
+  const bool out_col = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
+  const int y0 = blockIdx.y * A.rows;
+  const int y1 = min(y0 + A.rows, A.ny);
+  const double ax = A.alpha[0], ay = A.alpha[1];
+  const double dt = MODE == kRhs ? 0.0 : *A.dt;
+  if (MODE != kRhs && A.alpha_rec && blockIdx.x == 0 && blockIdx.y == 0 && lane == 0) {
+    A.alpha_rec[0] = ax;
+    A.alpha_rec[1] = ay;
+  }
+  const T hy = T(s.dy), ihy = T(s.idy), a_y = T(ay);
+
+  // register ring over rows (a = r-2, b = r-1 at the top of iteration r)
+  T Ua[NC], Ub[NC], Va[NC], Vb[NC], Wa[NC], Wb[NC];
+  T g3[NC], g2[NC], g1[NC], t3[NC], t2[NC], t1[NC], x3[NC], x2[NC], x1[NC];
+  T mGa[NC], mTa[NC], wta[NC];        // top-face LF halves and w~ of row r-2
+  T Fg[NC], Ft[NC], Fx[NC];           // y-interface fluxes at (r-3)+1/2
+  double smx = 0.0, smy = 0.0;
+  unsigned flag = 0;
+
+  T Un[NC], Vn[NC], Wn[NC];
+  load_row<Sys>(A, y0 - 2, gcol, Un, Vn, Wn);
+  for (int r = y0 - 2; r < y1 + 2; ++r) {
+    T Uc[NC], Vc[NC], Wc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) { Uc[c] = Un[c]; Vc[c] = Vn[c]; Wc[c] = Wn[c]; }
+    if (r + 1 < y1 + 2) load_row<Sys>(A, r + 1, gcol, Un, Vn, Wn);  // prefetch
+    // pointwise g, theta = g'(u) w, xi = g'(u) v of row r
+    T gc[NC], tc[NC], xc[NC];
+    {
+      const auto q = sy.prim(Uc);
+      sy.template flux<1>(Uc, q, gc);
+      sy.template jac<1>(Uc, q, Wc, tc);
+      sy.template jac<1>(Uc, q, Vc, xc);
+    }
+    // HWENO in y of row r-1 (rows r-2, r-1, r are present)
+    T mG[NC], mT[NC], pG[NC], pT[NC], wtn[NC];
+    if (r >= y0) {
+      T uT[NC], uB[NC], wT[NC], wB[NC];
+      hweno_cell<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, uT, uB, wtn);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) face_derivs(Ua[c], Ub[c], Uc[c], Wa[c], Wc[c], ihy, wT[c], wB[c]);
+      T gt[NC], tt[NC], gb[NC], tb[NC];
+      const auto qt = sy.prim(uT);
+      sy.template flux<1>(uT, qt, gt);
+      sy.template jac<1>(uT, qt, wT, tt);
+      const auto qb = sy.prim(uB);
+      sy.template flux<1>(uB, qb, gb);
+      sy.template jac<1>(uB, qb, wB, tb);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        mG[c] = T(0.5) * (gt[c] + a_y * uT[c]);
+        mT[c] = T(0.5) * (tt[c] + a_y * wT[c]);
+        pG[c] = T(0.5) * (gb[c] - a_y * uB[c]);
+        pT[c] = T(0.5) * (tb[c] - a_y * wB[c]);
+      }
+    }
+    if (r >= y0 + 1) {
+      // y-interface (r-2)+1/2: minus side = top face of row r-2, plus side =
+      // bottom face of row r-1; central correction from rows r-3..r
+      T Gn[NC], Tn[NC], Xn[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T Dg, Dt;
+        central_corr(g3[c], g2[c], g1[c], gc[c], t3[c], tc[c], hy, ihy, Dg, Dt);
+        Gn[c] = mGa[c] + pG[c] + Dg;
+        Tn[c] = mTa[c] + pT[c] + Dt;
+        Xn[c] = mixed_face(x3[c], x2[c], x1[c], xc[c]);
+      }
+      if (r >= y0 + 2) {
+        // output row o = r - 2: x-sweep of that row, then Step 4 and RK
+        const int o = r - 2;
+        double RU[NC], RV[NC], RW[NC];
+        T vt[NC];
+        sweep_x<3>(sy, s, ax, Ua, Va, Wa, RU, RV, RW, vt);
+        if (out_col) {
+          T Unew[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double Lu = RU[c] - ((double)Gn[c] - (double)Fg[c]) * s.idy;
+            const double Lv = RV[c] - ((double)Xn[c] - (double)Fx[c]) * s.idy;
+            const double Lw = RW[c] - ((double)Tn[c] - (double)Ft[c]) * s.idy;
+            const int idx = c * A.plane + o * A.nx + col;
+            const double ub = MODE >= kStage2 ? (double)A.Ub[idx] : 0.0;
+            const double vb = MODE >= kStage2 ? (double)A.Vb[idx] : 0.0;
+            const double wb = MODE >= kStage2 ? (double)A.Wb[idx] : 0.0;
+            Unew[c] = (T)rk<MODE>((double)Ua[c], ub, dt, Lu);
+            A.Uo[idx] = Unew[c];
+            A.Vo[idx] = (T)rk<MODE>((double)vt[c], vb, dt, Lv);
+            A.Wo[idx] = (T)rk<MODE>((double)wta[c], wb, dt, Lw);
+            if (MODE == kStage1 || MODE == kRhs) {
+              A.Vt[idx] = vt[c];
+              A.Wt[idx] = wta[c];
+            }
+          }
+          if (A.alpha_next) {
+            smx = fmax(smx, sy.template speed<0>(Unew));
+            smy = fmax(smy, sy.template speed<1>(Unew));
+            flag |= sy.admissible(Unew);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { Fg[c] = Gn[c]; Ft[c] = Tn[c]; Fx[c] = Xn[c]; }
+    }
+    // rotate the ring
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      g3[c] = g2[c]; g2[c] = g1[c]; g1[c] = gc[c];
+      t3[c] = t2[c]; t2[c] = t1[c]; t1[c] = tc[c];
+      x3[c] = x2[c]; x2[c] = x1[c]; x1[c] = xc[c];
+      Ua[c] = Ub[c]; Ub[c] = Uc[c];
+      Va[c] = Vb[c]; Vb[c] = Vc[c];
+      Wa[c] = Wb[c]; Wb[c] = Wc[c];
+      if (r >= y0) { mGa[c] = mG[c]; mTa[c] = mT[c]; wta[c] = wtn[c]; }
+    }
+  }
+  if (A.alpha_next) {
+    smx = wave_max(smx);
+    smy = wave_max(smy);
+    flag = wave_or(flag);
+    if (lane == 0) {
+      atomic_max_pos(A.alpha_next, smx);
+      atomic_max_pos(A.alpha_next + 1, smy);
+      if (flag && A.flags) atomicOr(A.flags, flag);
+    }
+  }
+}
+
+// ------------------------------------------------- wave-speed reduction (a2)
+// Per-block maxima of the spectral radius over interior cells, in x and y;
+// also raises the state flags.
+template <class Sys, typename T, int DIM>
+__global__ __launch_bounds__(256) void speed_partial_kernel(const T* U, int plane, Sys sy,
+                                                            double* partial, unsigned* flags) {
+  constexpr int NC = Sys::NC;
+  double mx = 0.0, my = 0.0;
+  unsigned flag = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += gridDim.x * blockDim.x) {
+    T u[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u[c] = U[c * plane + i];
+    mx = fmax(mx, sy.template speed<0>(u));
+    if (DIM == 2) my = fmax(my, sy.template speed<1>(u));
+    flag |= sy.admissible(u);
+  }
+  __shared__ double sx[4], sy_[4];
+  __shared__ unsigned sf[4];
+  mx = wave_max(mx);
+  my = wave_max(my);
+  flag = wave_or(flag);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { sx[w] = mx; sy_[w] = my; sf[w] = flag; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    for (int k = 1; k < nw; ++k) { mx = fmax(mx, sx[k]); my = fmax(my, sy_[k]); flag |= sf[k]; }
+    partial[2 * blockIdx.x] = mx;
+    partial[2 * blockIdx.x + 1] = my;
+    if (flag && flags) atomicOr(flags, flag);
+  }
+}
+
+__device__ void reduce_partials(const double* partial, int n, double* ax, double* ay) {
+  __shared__ double rx[256], ry[256];
+  double mx = 0.0, my = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    mx = fmax(mx, partial[2 * i]);
+    my = fmax(my, partial[2 * i + 1]);
+  }
+  rx[threadIdx.x] = mx;
+  ry[threadIdx.x] = my;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      rx[threadIdx.x] = fmax(rx[threadIdx.x], rx[threadIdx.x + st]);
+      ry[threadIdx.x] = fmax(ry[threadIdx.x], ry[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  *ax = rx[0];
+  *ay = ry[0];
+}
+
+__global__ __launch_bounds__(256) void alpha_out_kernel(const double* partial, int n, double* alpha) {
+  double ax, ay;
+  reduce_partials(partial, n, &ax, &ay);
+  if (threadIdx.x == 0) { alpha[0] = ax; alpha[1] = ay; }
+}
+
+// Workspace scalars of one time step.
+struct StepScalars {
+  double alpha1[2];               // stage-1 alphas
+  unsigned long long acc[4];      // stage-2 and stage-3 alphas (atomic max bits)
+  double dt;
+  int active;
+  unsigned flags;
+};
+
+// Delta t of the step from the stage-1 alphas (a2), clipped to t_end; also
+// arms the stage-2/3 alpha accumulators.
+struct DtArgs {
+  int rule;
+  double cfl, dt_fixed, t_end;
+  double hx, hy;   // dx, dy (production) or dx^(5/3), dy^(5/3) (accuracy)
+  int dim;
+};
+
+__global__ __launch_bounds__(256) void dt_kernel(const double* partial, int n, DtArgs a,
+                                                 StepScalars* sc, double* t, double* dt_used,
+                                                 double* alpha_rec) {
+  double ax, ay;
+  reduce_partials(partial, n, &ax, &ay);
+  if (threadIdx.x != 0) return;
+  if (a.dim == 1) ay = 0.0;
+  sc->alpha1[0] = ax;
+  sc->alpha1[1] = ay;
+  for (int k = 0; k < 4; ++k) sc->acc[k] = 0ull;
+  if (alpha_rec) { alpha_rec[0] = ax; alpha_rec[1] = ay; }
+  double dt;
+  if (a.rule == HWENO_DT_FIXED) dt = a.dt_fixed;
+  else dt = a.cfl / (a.dim == 2 ? ax / a.hx + ay / a.hy : ax / a.hx);
+  const double t0 = *t;
+  int active = t0 < a.t_end ? 1 : 0;
+  if (active) {
+    if (t0 + dt >= a.t_end) {
+      dt = a.t_end - t0;
+      *t = a.t_end;
+    } else {
+      *t = t0 + dt;
+    }
+  } else {
+    dt = 0.0;
+  }
+  sc->dt = dt;
+  sc->active = active;
+  if (dt_used) *dt_used = dt;
+}
+
+__global__ void ws_init_kernel(StepScalars* sc) {
+  sc->alpha1[0] = sc->alpha1[1] = 0.0;
+  for (int k = 0; k < 4; ++k) sc->acc[k] = 0ull;
+  sc->dt = 0.0;
+  sc->active = 0;
+  sc->flags = 0u;
+}
+
+}  // namespace hweno
+
+// =================================================================== host side
+using namespace hweno;
+
+namespace {
+
+constexpr size_t kScalarBytes = 4096;
+constexpr int kPartialBlocks = 1024;
+constexpr size_t kPartialBytes = kPartialBlocks * 2 * sizeof(double);
+constexpr int kRowsPerBlock = 32;
+
+struct Geometry {
+  int nc, nf;           // components; fields per state (2 in 1D: u, v; 3 in 2D)
+  size_t esize;         // element size
+  size_t plane;         // cells
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hweno_status validate(const hweno_problem* p) {
+  if (!p) return HWENO_EINVAL;
+  if (p->dim != 1 && p->dim != 2) return HWENO_EINVAL;
+  if (p->nx < 5) return HWENO_EINVAL;
+  if (p->dim == 2 && p->ny < 5) return HWENO_EINVAL;
+  if (p->dim == 1 && p->ny != 1) return HWENO_EINVAL;
+  if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return HWENO_EINVAL;
+  if (p->dim == 2 && (!(p->dy > 0.0) || !std::isfinite(p->dy))) return HWENO_EINVAL;
+  if (p->system < HWENO_ADVECTION || p->system > HWENO_EULER) return HWENO_EINVAL;
+  if (p->system == HWENO_EULER && !(p->gas_gamma > 1.0)) return HWENO_EINVAL;
+  if (p->system == HWENO_ADVECTION && (!std::isfinite(p->adv_a) || !std::isfinite(p->adv_b)))
+    return HWENO_EINVAL;
+  if (!(p->gamma0 > 0.0 && p->gamma0 < 1.0)) return HWENO_EINVAL;
+  if (!(p->d0 > 0.0 && p->d0 < 1.0)) return HWENO_EINVAL;
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return HWENO_EINVAL;
+  for (int k = 0; k < 4; ++k)
+    if (p->bc[k] != HWENO_PERIODIC && p->bc[k] != HWENO_TRANSMISSIVE) return HWENO_EINVAL;
+  if ((p->bc[0] == HWENO_PERIODIC) != (p->bc[1] == HWENO_PERIODIC)) return HWENO_EINVAL;
+  if (p->dim == 2 && (p->bc[2] == HWENO_PERIODIC) != (p->bc[3] == HWENO_PERIODIC))
+    return HWENO_EINVAL;
+  if (p->precision != HWENO_F64 && p->precision != HWENO_F32) return HWENO_EINVAL;
+  const int nc = p->system == HWENO_EULER ? p->dim + 2 : 1;
+  // 32-bit element offsets inside a state array
+  if ((double)nc * (double)p->nx * (double)p->ny >= 2147483647.0) return HWENO_EINVAL;
+  return HWENO_OK;
+}
+
+Geometry geometry(const hweno_problem* p) {
+  Geometry g;
+  g.nc = p->system == HWENO_EULER ? p->dim + 2 : 1;
+  g.nf = p->dim == 1 ? 2 : 3;
+  g.esize = p->precision == HWENO_F64 ? 8 : 4;
+  g.plane = (size_t)p->nx * (size_t)p->ny;
+  return g;
+}
+
+// Workspace: scalars | per-block partial maxima | states.
+// States are stored densely ([field][comp][ny][nx]); each region starts on a
+// 256-byte boundary. Regions: X^(1), X^(2), the RK base derivatives
+// (V~^n[, W~^n]) and three adjoint states.
+struct WsLayout {
+  StepScalars* sc;
+  double* partial;
+  char* x1;
+  char* x2;
+  char* base;
+  char* adj;
+  size_t state_bytes;
+};
+
+size_t state_bytes(const Geometry& g) { return align_up((size_t)g.nf * g.nc * g.plane * g.esize, 256); }
+size_t base_bytes(const Geometry& g) { return align_up((size_t)(g.nf - 1) * g.nc * g.plane * g.esize, 256); }
+size_t ws_total(const Geometry& g) {
+  return kScalarBytes + kPartialBytes + 5 * state_bytes(g) + base_bytes(g);
+}
+
+WsLayout ws_layout(void* ws, const Geometry& g) {
+  WsLayout w;
+  char* b = (char*)ws;
+  w.sc = (StepScalars*)b;
+  w.partial = (double*)(b + kScalarBytes);
+  w.state_bytes = state_bytes(g);
+  w.x1 = b + kScalarBytes + kPartialBytes;
+  w.x2 = w.x1 + w.state_bytes;
+  w.base = w.x2 + w.state_bytes;
+  w.adj = w.base + base_bytes(g);
+  return w;
+}
+
+Scheme make_scheme(const hweno_problem* p) {
+  Scheme s;
+  s.dx = p->dx;
+  s.dy = p->dim == 2 ? p->dy : 1.0;
+  s.idx = 1.0 / s.dx;
+  s.idy = 1.0 / s.dy;
+  s.gamma0 = p->gamma0;
+  s.g1 = 0.5 * (1.0 - p->gamma0);
+  s.d0 = p->d0;
+  s.d1 = 0.5 * (1.0 - p->d0);
+  s.eps = p->eps;
+  s.gas = p->gas_gamma;
+  s.adv_a = p->adv_a;
+  s.adv_b = p->adv_b;
+  return s;
+}
+
+inline hweno_status check_launch() {
+  return hipGetLastError() == hipSuccess ? HWENO_OK : HWENO_EDEVICE;
+}
+
+// Calls f(Sys{}, T{}, DIM) for the problem's system, element type and dimension.
+template <class F>
+hweno_status dispatch(const hweno_problem* p, F&& f) {
+  auto by_type = [&](auto tag) -> hweno_status {
+    using T = decltype(tag);
+    if (p->dim == 1) {
+      switch (p->system) {
+        case HWENO_ADVECTION: return f(Advection{p->adv_a, p->adv_b}, T{}, std::integral_constant<int, 1>{});
+        case HWENO_BURGERS: return f(Burgers{}, T{}, std::integral_constant<int, 1>{});
+        default: return f(Euler<1>{p->gas_gamma}, T{}, std::integral_constant<int, 1>{});
+      }
+    }
+    switch (p->system) {
+      case HWENO_ADVECTION: return f(Advection{p->adv_a, p->adv_b}, T{}, std::integral_constant<int, 2>{});
+      case HWENO_BURGERS: return f(Burgers{}, T{}, std::integral_constant<int, 2>{});
+      default: return f(Euler<2>{p->gas_gamma}, T{}, std::integral_constant<int, 2>{});
+    }
+  };
+  return p->precision == HWENO_F64 ? by_type(double{}) : by_type(float{});
+}
+
+template <class Sys, typename T, int DIM>
+hweno_status launch_stage(int mode, const StageArgs<T>& A, const Sys& sy, hipStream_t st) {
+  if constexpr (DIM == 1) {
+    dim3 grid((A.nx + kXOut - 1) / kXOut);
+    switch (mode) {
+      case kRhs: stage1d_kernel<Sys, T, kRhs><<<grid, kWave, 0, st>>>(A, sy); break;
+      case kStage1: stage1d_kernel<Sys, T, kStage1><<<grid, kWave, 0, st>>>(A, sy); break;
+      case kStage2: stage1d_kernel<Sys, T, kStage2><<<grid, kWave, 0, st>>>(A, sy); break;
+      default: stage1d_kernel<Sys, T, kStage3><<<grid, kWave, 0, st>>>(A, sy); break;
+    }
+  } else {
+    dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
+    switch (mode) {
+      case kRhs: stage2d_kernel<Sys, T, kRhs><<<grid, kWave, 0, st>>>(A, sy); break;
+      case kStage1: stage2d_kernel<Sys, T, kStage1><<<grid, kWave, 0, st>>>(A, sy); break;
+      case kStage2: stage2d_kernel<Sys, T, kStage2><<<grid, kWave, 0, st>>>(A, sy); break;
+      default: stage2d_kernel<Sys, T, kStage3><<<grid, kWave, 0, st>>>(A, sy); break;
+    }
+  }
+  return check_launch();
+}
+
+template <typename T>
+StageArgs<T> base_args(const hweno_problem* p) {
+  StageArgs<T> A;
+  std::memset(&A, 0, sizeof(A));
+  A.nx = p->nx;
+  A.ny = p->ny;
+  A.rows = kRowsPerBlock;
+  A.plane = p->nx * p->ny;
+  for (int k = 0; k < 4; ++k) A.bc[k] = p->bc[k];
+  A.s = make_scheme(p);
+  return A;
+}
+
+int partial_blocks(size_t plane) {
+  size_t b = (plane + 255) / 256;
+  return (int)(b < (size_t)kPartialBlocks ? b : (size_t)kPartialBlocks);
+}
+
+template <class Sys, typename T, int DIM>
+hweno_status launch_speed_partial(const hweno_problem* p, const T* U, const Sys& sy, double* partial,
+                                  unsigned* flags, hipStream_t st, int* nb) {
+  const size_t plane = (size_t)p->nx * p->ny;
+  *nb = partial_blocks(plane);
+  speed_partial_kernel<Sys, T, DIM><<<*nb, 256, 0, st>>>(U, (int)plane, sy, partial, flags);
+  return check_launch();
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* hweno_status_string(hweno_status s) {
+  switch (s) {
+    case HWENO_OK: return "ok";
+    case HWENO_EINVAL: return "invalid argument";
+    case HWENO_EUNSUPPORTED: return "unsupported";
+    case HWENO_EDEVICE: return "HIP runtime error";
+    case HWENO_ENONFINITE: return "non-finite state";
+    case HWENO_ENONPHYSICAL: return "non-physical state (density or pressure <= 0)";
+  }
+  return "unknown status";
+}
+
+hweno_status hweno_workspace_bytes(const hweno_problem* p, size_t* bytes) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!bytes) return HWENO_EINVAL;
+  const Geometry g = geometry(p);
+  *bytes = ws_total(g);
+  return HWENO_OK;
+}
+
+hweno_status hweno_workspace_init(const hweno_problem* p, void* ws, hipStream_t stream) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!ws) return HWENO_EINVAL;
+  ws_init_kernel<<<1, 1, 0, stream>>>((StepScalars*)ws);
+  return check_launch();
+}
+
+hweno_status hweno_max_wavespeed(const hweno_problem* p, const void* u, double* alpha, void* ws,
+                                 hipStream_t stream) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!u || !alpha || !ws) return HWENO_EINVAL;
+  const Geometry g = geometry(p);
+  WsLayout w = ws_layout(ws, g);
+  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
+    using T = decltype(tag);
+    using Sys = decltype(sy);
+    constexpr int DIM = decltype(dimc)::value;
+    int nb;
+    hweno_status s2 = launch_speed_partial<Sys, T, DIM>(p, (const T*)u, sy, w.partial,
+                                                        &w.sc->flags, stream, &nb);
+    if (s2 != HWENO_OK) return s2;
+    alpha_out_kernel<<<1, 256, 0, stream>>>(w.partial, nb, alpha);
+    return check_launch();
+  });
+}
+
+hweno_status hweno_rhs(const hweno_problem* p, const void* u, const void* v, const void* w,
+                       const double* alpha, void* Lu, void* Lv, void* Lw, void* vtilde,
+                       void* wtilde, void* ws, hipStream_t stream) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!u || !v || !alpha || !Lu || !Lv || !vtilde || !ws) return HWENO_EINVAL;
+  if (p->dim == 2 && (!w || !Lw || !wtilde)) return HWENO_EINVAL;
+  if (p->dim == 1 && (w || Lw || wtilde)) return HWENO_EINVAL;
+  const void* ins[3] = {u, v, w};
+  void* outs[5] = {Lu, Lv, Lw, vtilde, wtilde};
+  for (auto o : outs)
+    for (auto i : ins)
+      if (o && i && o == i) return HWENO_EINVAL;
+  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
+    using T = decltype(tag);
+    using Sys = decltype(sy);
+    constexpr int DIM = decltype(dimc)::value;
+    StageArgs<T> A = base_args<T>(p);
+    A.U = (const T*)u; A.V = (const T*)v; A.W = (const T*)w;
+    A.Uo = (T*)Lu; A.Vo = (T*)Lv; A.Wo = (T*)Lw;
+    A.Vt = (T*)vtilde; A.Wt = (T*)wtilde;
+    A.alpha = alpha;
+    return launch_stage<Sys, T, DIM>(kRhs, A, sy, stream);
+  });
+}
+
+hweno_status hweno_step(const hweno_problem* p, void* u, void* v, void* w, int32_t dt_rule,
+                        double cfl, double dt_fixed, double t_end, double* t, double* dt_used,
+                        double* alpha_rec, void* stages, void* ws, hipStream_t stream) {
+  return hweno_step_profiled(p, u, v, w, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec,
+                             stages, ws, stream, nullptr);
+}
+
+hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void* w,
+                                 int32_t dt_rule, double cfl, double dt_fixed, double t_end,
+                                 double* t, double* dt_used, double* alpha_rec, void* stages,
+                                 void* ws, hipStream_t stream, hipEvent_t* events) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!u || !v || !t || !ws) return HWENO_EINVAL;
+  if (p->dim == 2 && !w) return HWENO_EINVAL;
+  if (p->dim == 1 && w) return HWENO_EINVAL;
+  if (dt_rule < HWENO_DT_PRODUCTION || dt_rule > HWENO_DT_FIXED) return HWENO_EINVAL;
+  if (dt_rule == HWENO_DT_FIXED ? !(dt_fixed > 0.0) : !(cfl > 0.0)) return HWENO_EINVAL;
+  if (std::isnan(t_end)) return HWENO_EINVAL;
+  const Geometry g = geometry(p);
+  WsLayout wl = ws_layout(ws, g);
+  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
+    using T = decltype(tag);
+    using Sys = decltype(sy);
+    constexpr int DIM = decltype(dimc)::value;
+    const size_t P = g.plane;
+    // stage states: the caller's `stages` buffer when given, else the workspace
+    char* x1 = stages ? (char*)stages : wl.x1;
+    char* x2 = stages ? (char*)stages + (size_t)g.nf * g.nc * P * sizeof(T) : wl.x2;
+    T* Vt = (T*)wl.base;
+    T* Wt = DIM == 2 ? Vt + (size_t)g.nc * P : nullptr;
+    auto F = [&](char* b, int f) { return (T*)(b + (size_t)f * g.nc * P * sizeof(T)); };
+    // stage-1 alphas and dt
+    int nb;
+    hweno_status s2 = launch_speed_partial<Sys, T, DIM>(p, (const T*)u, sy, wl.partial,
+                                                        &wl.sc->flags, stream, &nb);
+    if (s2 != HWENO_OK) return s2;
+    DtArgs da;
+    da.rule = dt_rule;
+    da.cfl = cfl;
+    da.dt_fixed = dt_fixed;
+    da.t_end = t_end;
+    da.dim = DIM;
+    if (dt_rule == HWENO_DT_ACCURACY) {
+      da.hx = std::pow(p->dx, 5.0 / 3.0);
+      da.hy = DIM == 2 ? std::pow(p->dy, 5.0 / 3.0) : 1.0;
+    } else {
+      da.hx = p->dx;
+      da.hy = DIM == 2 ? p->dy : 1.0;
+    }
+    dt_kernel<<<1, 256, 0, stream>>>(wl.partial, nb, da, wl.sc, t, dt_used, alpha_rec);
+    if ((s2 = check_launch()) != HWENO_OK) return s2;
+    StageArgs<T> A = base_args<T>(p);
+    A.dt = &wl.sc->dt;
+    A.active = &wl.sc->active;
+    A.flags = &wl.sc->flags;
+    auto mark = [&](int k) -> bool {
+      return !events || hipEventRecord(events[k], stream) == hipSuccess;
+    };
+    // stage 1: X^n -> X^(1), V~^n, W~^n
+    if (!mark(0)) return HWENO_EDEVICE;
+    A.U = (const T*)u; A.V = (const T*)v; A.W = (const T*)w;
+    A.Uo = F(x1, 0); A.Vo = F(x1, 1); A.Wo = DIM == 2 ? F(x1, 2) : nullptr;
+    A.Vt = Vt; A.Wt = Wt;
+    A.alpha = wl.sc->alpha1;
+    A.alpha_next = &wl.sc->acc[0];
+    A.alpha_rec = nullptr;
+    if ((s2 = launch_stage<Sys, T, DIM>(kStage1, A, sy, stream)) != HWENO_OK) return s2;
+    if (!mark(1)) return HWENO_EDEVICE;
+    // stage 2: X^(1) -> X^(2) with base (U^n, V~^n, W~^n)
+    A.U = F(x1, 0); A.V = F(x1, 1); A.W = DIM == 2 ? F(x1, 2) : nullptr;
+    A.Ub = (const T*)u; A.Vb = Vt; A.Wb = Wt;
+    A.Uo = F(x2, 0); A.Vo = F(x2, 1); A.Wo = DIM == 2 ? F(x2, 2) : nullptr;
+    A.Vt = nullptr; A.Wt = nullptr;
+    A.alpha = (const double*)&wl.sc->acc[0];
+    A.alpha_next = &wl.sc->acc[2];
+    A.alpha_rec = alpha_rec ? alpha_rec + 2 : nullptr;
+    if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
+    if (!mark(2)) return HWENO_EDEVICE;
+    // stage 3: X^(2) -> X^{n+1}, in place on (u, v, w)
+    A.U = F(x2, 0); A.V = F(x2, 1); A.W = DIM == 2 ? F(x2, 2) : nullptr;
+    A.Uo = (T*)u; A.Vo = (T*)v; A.Wo = (T*)w;
+    A.alpha = (const double*)&wl.sc->acc[2];
+    A.alpha_next = nullptr;
+    A.alpha_rec = alpha_rec ? alpha_rec + 4 : nullptr;
+    if ((s2 = launch_stage<Sys, T, DIM>(kStage3, A, sy, stream)) != HWENO_OK) return s2;
+    if (!mark(3)) return HWENO_EDEVICE;
+    return HWENO_OK;
+  });
+}
+
+hweno_status hweno_adjoint_step(const hweno_problem* p, const void*, const void*, const void*,
+                                const void*, const double*, const double*, const void*,
+                                const void*, const void*, void*, void*, void*, void*,
+                                hipStream_t) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  return HWENO_EUNSUPPORTED;
+}
+
+hweno_status hweno_health(const hweno_problem* p, void* ws, hipStream_t stream, int32_t clear) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!ws) return HWENO_EINVAL;
+  unsigned flags = 0;
+  StepScalars* sc = (StepScalars*)ws;
+  if (hipMemcpyAsync(&flags, &sc->flags, sizeof(unsigned), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return HWENO_EDEVICE;
+  if (hipStreamSynchronize(stream) != hipSuccess) return HWENO_EDEVICE;
+  if (clear) {
+    ws_init_kernel<<<1, 1, 0, stream>>>(sc);
+    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return HWENO_EDEVICE;
+  }
+  if (flags & 1u) return HWENO_ENONFINITE;
+  if (flags & 2u) return HWENO_ENONPHYSICAL;
+  return HWENO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+"""Python binding of ``libhweno.so`` (the HWENO-I C ABI, include/hweno.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels.
+Tensors are torch tensors on the HIP device, contiguous, float64 or float32
+(matching ``Problem.precision``), shaped ``[ncomp, nx]`` in 1D and
+``[ncomp, ny, nx]`` in 2D. Work is enqueued on torch's current stream.
+
+The library is loaded on first use; a missing library raises RuntimeError
+(there is no CPU fallback).
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libhweno.so')
+
+SYSTEMS = {'advection': 0, 'burgers': 1, 'euler': 2}
+BCS = {'periodic': 0, 'transmissive': 1}
+PRECISIONS = {'f64': 0, 'f32': 1}
+DT_RULES = {'production': 0, 'accuracy': 1, 'fixed': 2}
+STATUS = {0: 'ok', -1: 'invalid argument', -2: 'unsupported', -3: 'HIP runtime error',
+          -4: 'non-finite state', -5: 'non-physical state'}
+
+
+class HwenoError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f'{what}: {STATUS.get(code, code)} (status {code})')
+        self.code = code
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [('dim', ctypes.c_int32), ('nx', ctypes.c_int32), ('ny', ctypes.c_int32),
+                ('dx', ctypes.c_double), ('dy', ctypes.c_double), ('system', ctypes.c_int32),
+                ('adv_a', ctypes.c_double), ('adv_b', ctypes.c_double),
+                ('gas_gamma', ctypes.c_double), ('gamma0', ctypes.c_double),
+                ('d0', ctypes.c_double), ('eps', ctypes.c_double),
+                ('bc', ctypes.c_int32 * 4), ('precision', ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    'hweno_status_string': ([ctypes.c_int], ctypes.c_char_p),
+    'hweno_workspace_bytes': ([ctypes.POINTER(_CProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    'hweno_workspace_init': ([ctypes.POINTER(_CProblem), _P, _P], ctypes.c_int),
+    'hweno_max_wavespeed': ([ctypes.POINTER(_CProblem), _P, _P, _P, _P], ctypes.c_int),
+    'hweno_rhs': ([ctypes.POINTER(_CProblem)] + [_P] * 11, ctypes.c_int),
+    'hweno_step': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
+                    ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    'hweno_step_profiled': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P],
+                            ctypes.c_int),
+    'hweno_adjoint_step': ([ctypes.POINTER(_CProblem)] + [_P] * 14, ctypes.c_int),
+    'hweno_health': ([ctypes.POINTER(_CProblem), _P, _P, ctypes.c_int32], ctypes.c_int),
+}
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhweno.so (ctypes) and declare its signatures."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f'{path} is missing: build it with '
+                               '`python -m paper_2411_11229_amd.build` (no CPU fallback exists)')
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise HwenoError(code, what)
+
+
+@dataclass
+class Problem:
+    """Mirror of ``hweno_problem``. gamma0 defaults to 0.95 (1D) / 0.99 (2D)."""
+    dim: int
+    nx: int
+    dx: float
+    system: str
+    ny: int = 1
+    dy: float = 1.0
+    adv_a: float = 1.0
+    adv_b: float = 1.0
+    gas_gamma: float = 1.4
+    gamma0: float = None
+    d0: float = 0.9
+    eps: float = 1e-10
+    bc: tuple = ('periodic',) * 4
+    precision: str = 'f64'
+
+    def __post_init__(self):
+        if self.gamma0 is None:
+            self.gamma0 = 0.95 if self.dim == 1 else 0.99
+
+    @property
+    def ncomp(self):
+        return (self.dim + 2) if self.system == 'euler' else 1
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == 'f64' else torch.float32
+
+    @property
+    def shape(self):
+        return (self.ncomp, self.nx) if self.dim == 1 else (self.ncomp, self.ny, self.nx)
+
+    def c(self):
+        p = _CProblem()
+        p.dim, p.nx, p.ny = self.dim, self.nx, self.ny
+        p.dx, p.dy = self.dx, self.dy
+        p.system = SYSTEMS[self.system]
+        p.adv_a, p.adv_b, p.gas_gamma = self.adv_a, self.adv_b, self.gas_gamma
+        p.gamma0, p.d0, p.eps = self.gamma0, self.d0, self.eps
+        for k in range(4):
+            p.bc[k] = BCS[self.bc[k]]
+        p.precision = PRECISIONS[self.precision]
+        return p
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One problem plus its device workspace (allocated once by torch)."""
+
+    def __init__(self, prob, device='cuda'):
+        self.prob = prob
+        self.lib = load_library()
+        self.cp = _CProblem()
+        self.cp = prob.c()
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.hweno_workspace_bytes(ctypes.byref(self.cp), ctypes.byref(nbytes)),
+               'hweno_workspace_bytes')
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        _check(self.lib.hweno_workspace_init(ctypes.byref(self.cp), _ptr(self.ws),
+                                             _stream(self.device)), 'hweno_workspace_init')
+
+    # ------------------------------------------------------------ checks
+    def _state(self, t, name, allow_none=False):
+        if t is None:
+            if allow_none:
+                return None
+            raise ValueError(f'{name} is required')
+        if not isinstance(t, torch.Tensor) or t.device.type != 'cuda':
+            raise ValueError(f'{name} must be a HIP-device torch tensor')
+        if t.dtype != self.prob.dtype:
+            raise ValueError(f'{name}: dtype {t.dtype} != {self.prob.dtype}')
+        if tuple(t.shape) != self.prob.shape:
+            raise ValueError(f'{name}: shape {tuple(t.shape)} != {self.prob.shape}')
+        if not t.is_contiguous():
+            raise ValueError(f'{name} must be contiguous')
+        return t
+
+    def _alpha(self, a, name='alpha'):
+        if not (isinstance(a, torch.Tensor) and a.dtype == torch.float64 and a.numel() >= 2
+                and a.device.type == 'cuda' and a.is_contiguous()):
+            raise ValueError(f'{name} must be a contiguous float64 device tensor of 2 values')
+        return a
+
+    def new_state(self):
+        return torch.empty(self.prob.shape, dtype=self.prob.dtype, device=self.device)
+
+    # ------------------------------------------------------------ entry points
+    def max_wavespeed(self, U, out=None):
+        U = self._state(U, 'U')
+        out = torch.empty(2, dtype=torch.float64, device=self.device) if out is None else out
+        _check(self.lib.hweno_max_wavespeed(ctypes.byref(self.cp), _ptr(U), _ptr(self._alpha(out)),
+                                            _ptr(self.ws), _stream(self.device)),
+               'hweno_max_wavespeed')
+        return out
+
+    def rhs(self, U, V, W=None, alpha=None):
+        """(L1, L2, L3, vtilde, wtilde); L3, wtilde are None in 1D."""
+        two = self.prob.dim == 2
+        U, V = self._state(U, 'U'), self._state(V, 'V')
+        W = self._state(W, 'W') if two else None
+        alpha = self.max_wavespeed(U) if alpha is None else self._alpha(alpha)
+        L1, L2, vt = self.new_state(), self.new_state(), self.new_state()
+        L3 = self.new_state() if two else None
+        wt = self.new_state() if two else None
+        _check(self.lib.hweno_rhs(ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W), _ptr(alpha),
+                                  _ptr(L1), _ptr(L2), _ptr(L3), _ptr(vt), _ptr(wt), _ptr(self.ws),
+                                  _stream(self.device)), 'hweno_rhs')
+        return L1, L2, L3, vt, wt
+
+    def step(self, U, V, W, t, t_end=float('inf'), rule='production', cfl=0.6, dt_fixed=0.0,
+             dt_used=None, alpha_rec=None, stages=None, events=None):
+        """One SSP-RK3 step in place. ``t``: float64 device tensor (in/out).
+        ``events``: optional ctypes array of 4 hipEvent_t recorded around the
+        three stage launches (hweno_step_profiled)."""
+        two = self.prob.dim == 2
+        U, V = self._state(U, 'U'), self._state(V, 'V')
+        W = self._state(W, 'W') if two else None
+        for name, x, n in (('t', t, 1), ('dt_used', dt_used, 1), ('alpha_rec', alpha_rec, 6)):
+            if x is not None and not (x.dtype == torch.float64 and x.device.type == 'cuda'
+                                      and x.numel() >= n and x.is_contiguous()):
+                raise ValueError(f'{name} must be a contiguous float64 device tensor')
+        if stages is not None:
+            nf = 3 if two else 2
+            need = 2 * nf * self.prob.ncomp * self.prob.nx * self.prob.ny
+            if not (stages.dtype == self.prob.dtype and stages.numel() >= need
+                    and stages.is_contiguous() and stages.device.type == 'cuda'):
+                raise ValueError('stages: wrong dtype, size or layout')
+        args = (ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W), DT_RULES[rule], float(cfl),
+                float(dt_fixed), float(t_end), _ptr(t), _ptr(dt_used), _ptr(alpha_rec),
+                _ptr(stages), _ptr(self.ws), _stream(self.device))
+        if events is None:
+            _check(self.lib.hweno_step(*args), 'hweno_step')
+        else:
+            _check(self.lib.hweno_step_profiled(*args, events), 'hweno_step_profiled')
+
+    def adjoint_step(self, U, V, W, dt, alpha_rec, lam_in, lam_out, stages=None):
+        """dJ/dX^n into ``lam_out`` (3-tuple, or 2-tuple in 1D) from dJ/dX^{n+1}."""
+        two = self.prob.dim == 2
+        li = list(lam_in) + [None] * (3 - len(lam_in))
+        lo = list(lam_out) + [None] * (3 - len(lam_out))
+        _check(self.lib.hweno_adjoint_step(
+            ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W if two else None), _ptr(stages),
+            _ptr(dt), _ptr(alpha_rec), _ptr(li[0]), _ptr(li[1]), _ptr(li[2] if two else None),
+            _ptr(lo[0]), _ptr(lo[1]), _ptr(lo[2] if two else None), _ptr(self.ws),
+            _stream(self.device)), 'hweno_adjoint_step')
+
+    def health(self, clear=False):
+        """Sync the stream; raise HwenoError if a non-finite / non-physical
+        state was flagged since the last clear."""
+        _check(self.lib.hweno_health(ctypes.byref(self.cp), _ptr(self.ws), _stream(self.device),
+                                     1 if clear else 0), 'state check')
+
+    def run(self, U, V, W, t_end, rule='production', cfl=0.6, max_steps=None, chunk=32,
+            record=False):
+        """Advance in place to t_end (or max_steps). Steps are launched in
+        chunks; the device skips steps once t reaches t_end. Returns
+        (steps, t, dts[, alpha_recs]) with dts / alphas as device tensors."""
+        t = torch.zeros(1, dtype=torch.float64, device=self.device)
+        cap = max_steps if max_steps is not None else 1 << 30
+        dts, recs = [], []
+        n = 0
+        while n < cap:
+            k = min(chunk, cap - n)
+            buf = torch.zeros(k, dtype=torch.float64, device=self.device)
+            rec = torch.zeros(k, 6, dtype=torch.float64, device=self.device) if record else None
+            for j in range(k):
+                self.step(U, V, W, t, t_end, rule, cfl, dt_used=buf[j:j + 1],
+                          alpha_rec=rec[j] if record else None)
+            dts.append(buf)
+            if record:
+                recs.append(rec)
+            n += k
+            if float(t.item()) >= t_end:
+                break
+        dts = torch.cat(dts)
+        steps = int((dts > 0).sum().item())
+        out = (steps, float(t.item()), dts[:steps])
+        if record:
+            out = out + (torch.cat(recs)[:steps],)
+        return out
