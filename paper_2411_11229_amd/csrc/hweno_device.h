@@ -11,6 +11,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Per-point functions compile for the host too (a CPU harness checks the
+// adjoint of each against finite differences); lane shifts and kernels are
+// device-only.
+#define HWENO_HD __host__ __device__ __forceinline__
+
 namespace hweno {
 
 constexpr int kWave = 64;                 // lanes per wavefront (CDNA)
@@ -21,7 +26,7 @@ constexpr int kXOut = kWave - 2 * kHalo;  // output columns per wavefront
 struct Scheme {
   double dx, dy, idx, idy;  // mesh widths and their inverses
   double gamma0, g1;        // linear weights of (interp); g1 = gamma1 = gamma2
-  double d0, d1;            // linear weights of (limiter); d1 = d1 = d2
+  double d0, d1;            // linear weights of (limiter); d1 = d2
   double eps;               // epsilon of (nonlinear)
   double gas;               // ratio of specific heats (Euler)
   double adv_a, adv_b;      // advection speeds
@@ -29,10 +34,79 @@ struct Scheme {
 
 // ---------------------------------------------------------------- lane shifts
 // Values of the neighbouring lane along x (lanes are consecutive cells).
+// DPP wave_shr:1 / wave_shl:1 row moves: lane i receives lane i-1 / i+1 (a
+// lane without a source keeps its own value). They execute as VALU moves,
+// with no LDS round trip.
+__device__ __forceinline__ int dpp_prev_i32(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_next_i32(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false);
+}
+template <typename T> __device__ __forceinline__ T from_prev(T x);
+template <typename T> __device__ __forceinline__ T from_next(T x);
+template <>
+__device__ __forceinline__ double from_prev<double>(double x) {
+  return __hiloint2double(dpp_prev_i32(__double2hiint(x)), dpp_prev_i32(__double2loint(x)));
+}
+template <>
+__device__ __forceinline__ double from_next<double>(double x) {
+  return __hiloint2double(dpp_next_i32(__double2hiint(x)), dpp_next_i32(__double2loint(x)));
+}
+template <>
+__device__ __forceinline__ float from_prev<float>(float x) {
+  return __int_as_float(dpp_prev_i32(__float_as_int(x)));
+}
+template <>
+__device__ __forceinline__ float from_next<float>(float x) {
+  return __int_as_float(dpp_next_i32(__float_as_int(x)));
+}
 template <typename T>
-__device__ __forceinline__ T from_prev(T x) { return __shfl_up(x, 1); }
-template <typename T>
-__device__ __forceinline__ T from_next(T x) { return __shfl_down(x, 1); }
+__device__ __forceinline__ T from_next2(T x) { return from_next(from_next(x)); }
+
+// ---------------------------------------------------------------- reciprocals
+// Hardware reciprocal (square root) estimate refined by Newton steps: within
+// an ulp or two of the correctly rounded value, for the positive, finite,
+// normal arguments the scheme produces, at half the instructions of an IEEE
+// division.
+HWENO_HD double rcp_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+HWENO_HD float rcp_nr(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+#else
+  return 1.0f / x;
+#endif
+}
+HWENO_HD double rsqrt_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  // y <- y (3 - x y^2) / 2, twice
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+HWENO_HD float rsqrt_nr(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  float y = __builtin_amdgcn_rsqf(x);
+  return y * fmaf(-0.5f * x * y, y, 1.5f);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
 
 // ---------------------------------------------------------------- HWENO-I
 // One HWENO-I application on one scalar line (a conserved component for the
@@ -48,7 +122,7 @@ __device__ __forceinline__ T from_next(T x) { return __shfl_down(x, 1); }
 // which needs gamma1 = gamma2 (the paper's choice). The three ratios share
 // one division, and both normalisations share another.
 template <typename T>
-__device__ __forceinline__ void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
+HWENO_HD void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
                                             double h, double ih, T& uR, T& uL, T& vt) {
   const double dm = (double)um, dc = (double)u0, dp = (double)up;
   const double sv = 0.25 * h * ((double)vm + (double)vp);
@@ -71,13 +145,13 @@ __device__ __forceinline__ void hweno_point(T um, T u0, T up, T vm, T vp, const 
   const double tau = 0.25 * ts * ts;
   const double q0 = b0 + s.eps, q1 = b1 + s.eps, q2 = b2 + s.eps;
   const double q12 = q1 * q2;
-  const double ti = tau / (q0 * q12);
+  const double ti = tau * rcp_nr(q0 * q12);
   const double o0 = 1.0 + ti * q12;           // 1 + tau/(beta0+eps)
   const double o1 = 1.0 + ti * (q0 * q2);     // 1 + tau/(beta1+eps)
   const double o2 = 1.0 + ti * (q0 * q1);     // 1 + tau/(beta2+eps)
   const double Sg = s.gamma0 * o0 + s.g1 * (o1 + o2);
   const double Sd = s.d0 * o0 + s.d1 * (o1 + o2);
-  const double inv = 1.0 / (Sg * Sd);
+  const double inv = rcp_nr(Sg * Sd);
   const double iSg = Sd * inv, iSd = Sg * inv;
   // (Pxi): candidates at x_{i+1/2}
   const double vmd = (double)vm, vpd = (double)vp;
@@ -100,7 +174,7 @@ __device__ __forceinline__ void hweno_point(T um, T u0, T up, T vm, T vp, const 
 // (P'xi) and its mirror: v^-_{i+1/2} = p0'(x_{i+1/2}), v^+_{i-1/2} = p0'(x_{i-1/2}).
 // Linear in the data, hence the same in conserved or characteristic variables.
 template <typename T>
-__device__ __forceinline__ void face_derivs(T um, T u0, T up, T vm, T vp, T ih, T& vR, T& vL) {
+HWENO_HD void face_derivs(T um, T u0, T up, T vm, T vp, T ih, T& vR, T& vL) {
   vR = (T(0.1875) * um - T(1.5) * u0 + T(1.3125) * up) * ih + T(0.0625) * vm - T(0.1875) * vp;
   vL = (T(-1.3125) * um + T(1.5) * u0 - T(0.1875) * up) * ih - T(0.1875) * vm + T(0.0625) * vp;
 }
@@ -110,7 +184,7 @@ __device__ __forceinline__ void face_derivs(T um, T u0, T up, T vm, T vp, T ih, 
 //   D(h) = [697/5184 (f_{i-1} - f_{i+2}) - 61/192 (f_i - f_{i+1})] / dx
 //          + 37/864 (h_{i-1} + h_{i+2})
 template <typename T>
-__device__ __forceinline__ void central_corr(T fm1, T f0, T fp1, T fp2, T hm1, T hp2, T h, T ih,
+HWENO_HD void central_corr(T fm1, T f0, T fp1, T fp2, T hm1, T hp2, T h, T ih,
                                              T& Df, T& Dh) {
   const T s4 = (fm1 + fp2) - (f0 + fp1);
   Df = T(-97.0 / 1920.0) * s4 - T(19.0 / 960.0) * h * (hm1 - hp2);
@@ -120,7 +194,7 @@ __device__ __forceinline__ void central_corr(T fm1, T f0, T fp1, T fp2, T hm1, T
 
 // (mixed): interface value of a mixed-derivative flux.
 template <typename T>
-__device__ __forceinline__ T mixed_face(T em1, T e0, T ep1, T ep2) {
+HWENO_HD T mixed_face(T em1, T e0, T ep1, T ep2) {
   return (T(7.0) * (e0 + ep1) - (em1 + ep2)) * T(1.0 / 12.0);
 }
 
@@ -138,20 +212,20 @@ struct Advection {
   double a, b;
   template <typename T> struct Prim {};
   template <typename T>
-  __device__ __forceinline__ Prim<T> prim(const T (&)[NC]) const { return {}; }
+  HWENO_HD Prim<T> prim(const T (&)[NC]) const { return {}; }
   template <int D, typename T>
-  __device__ __forceinline__ void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
+  HWENO_HD void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
     F[0] = T(D == 0 ? a : b) * U[0];
   }
   template <int D, typename T>
-  __device__ __forceinline__ void jac(const T (&)[NC], const Prim<T>&, const T (&V)[NC],
+  HWENO_HD void jac(const T (&)[NC], const Prim<T>&, const T (&V)[NC],
                                       T (&O)[NC]) const {
     O[0] = T(D == 0 ? a : b) * V[0];
   }
   template <int D, typename T>
-  __device__ __forceinline__ double speed(const T (&)[NC]) const { return fabs(D == 0 ? a : b); }
+  HWENO_HD double speed(const T (&)[NC]) const { return fabs(D == 0 ? a : b); }
   template <typename T>
-  __device__ __forceinline__ unsigned admissible(const T (&U)[NC]) const {
+  HWENO_HD unsigned admissible(const T (&U)[NC]) const {
     return isfinite((double)U[0]) ? 0u : 1u;
   }
 };
@@ -161,20 +235,20 @@ struct Burgers {
   static constexpr bool kChar = false;
   template <typename T> struct Prim {};
   template <typename T>
-  __device__ __forceinline__ Prim<T> prim(const T (&)[NC]) const { return {}; }
+  HWENO_HD Prim<T> prim(const T (&)[NC]) const { return {}; }
   template <int D, typename T>
-  __device__ __forceinline__ void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
+  HWENO_HD void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
     F[0] = T(0.5) * U[0] * U[0];
   }
   template <int D, typename T>
-  __device__ __forceinline__ void jac(const T (&U)[NC], const Prim<T>&, const T (&V)[NC],
+  HWENO_HD void jac(const T (&U)[NC], const Prim<T>&, const T (&V)[NC],
                                       T (&O)[NC]) const {
     O[0] = U[0] * V[0];
   }
   template <int D, typename T>
-  __device__ __forceinline__ double speed(const T (&U)[NC]) const { return fabs((double)U[0]); }
+  HWENO_HD double speed(const T (&U)[NC]) const { return fabs((double)U[0]); }
   template <typename T>
-  __device__ __forceinline__ unsigned admissible(const T (&U)[NC]) const {
+  HWENO_HD unsigned admissible(const T (&U)[NC]) const {
     return isfinite((double)U[0]) ? 0u : 1u;
   }
 };
@@ -193,9 +267,9 @@ struct Euler {
     T ir, mu, nu, k, p, Ep;  // 1/rho, u, v, |vel|^2/2, P, E + P
   };
   template <typename T>
-  __device__ __forceinline__ Prim<T> prim(const T (&U)[NC]) const {
+  HWENO_HD Prim<T> prim(const T (&U)[NC]) const {
     Prim<T> q;
-    q.ir = T(1) / U[0];
+    q.ir = rcp_nr(U[0]);
     q.mu = U[1] * q.ir;
     q.nu = DIM == 2 ? U[2] * q.ir : T(0);
     q.k = T(0.5) * (q.mu * q.mu + q.nu * q.nu);
@@ -204,7 +278,7 @@ struct Euler {
     return q;
   }
   template <int D, typename T>
-  __device__ __forceinline__ void flux(const T (&U)[NC], const Prim<T>& q, T (&F)[NC]) const {
+  HWENO_HD void flux(const T (&U)[NC], const Prim<T>& q, T (&F)[NC]) const {
     if constexpr (DIM == 1) {
       F[0] = U[1];
       F[1] = U[1] * q.mu + q.p;
@@ -225,7 +299,7 @@ struct Euler {
   // along V, du = (V1 - u V0)/rho, dv = (V2 - v V0)/rho and
   // dP = (gas-1)(V_E - u V1 - v V2 + k V0).
   template <int D, typename T>
-  __device__ __forceinline__ void jac(const T (&U)[NC], const Prim<T>& q, const T (&V)[NC],
+  HWENO_HD void jac(const T (&U)[NC], const Prim<T>& q, const T (&V)[NC],
                                       T (&O)[NC]) const {
     const T gm1 = T(gas - 1.0);
     if constexpr (DIM == 1) {
@@ -261,21 +335,21 @@ struct Euler {
     T mu, nu, k, c, ic, H, b1, b2;
   };
   template <typename T>
-  __device__ __forceinline__ Eig<T> eig(const Prim<T>& q) const {
+  HWENO_HD Eig<T> eig(const Prim<T>& q) const {
     Eig<T> e;
     e.mu = q.mu;
     e.nu = q.nu;
     e.k = q.k;
     const T c2 = T(gas) * q.p * q.ir;
-    e.c = sqrt(c2);
-    e.ic = T(1) / e.c;
+    e.ic = rsqrt_nr(c2);
+    e.c = c2 * e.ic;
     e.H = q.Ep * q.ir;
     e.b1 = T(gas - 1.0) * e.ic * e.ic;
     e.b2 = e.b1 * q.k;
     return e;
   }
   template <int D, typename T>
-  __device__ __forceinline__ void left(const Eig<T>& e, int j, T (&l)[NC]) const {
+  HWENO_HD void left(const Eig<T>& e, int j, T (&l)[NC]) const {
     const T vn = D == 0 ? e.mu : e.nu;    // normal velocity
     if constexpr (DIM == 1) {
       if (j == 0) { l[0] = T(0.5) * (e.b2 + e.mu * e.ic); l[1] = T(-0.5) * (e.b1 * e.mu + e.ic); l[2] = T(0.5) * e.b1; }
@@ -301,7 +375,7 @@ struct Euler {
     }
   }
   template <int D, typename T>
-  __device__ __forceinline__ void right(const Eig<T>& e, int j, T (&r)[NC]) const {
+  HWENO_HD void right(const Eig<T>& e, int j, T (&r)[NC]) const {
     const T vn = D == 0 ? e.mu : e.nu;
     if constexpr (DIM == 1) {
       if (j == 0) { r[0] = T(1); r[1] = e.mu - e.c; r[2] = e.H - e.mu * e.c; }
@@ -322,8 +396,51 @@ struct Euler {
       }
     }
   }
+  // w = L U and U = R c for the basis above, with the shared terms of the
+  // rows (columns) collected: for x in 2D, with s = b2 U0 - b1 (u U1 + v U2
+  // - UE) and t = (u U0 - U1)/c, L U = ((s+t)/2, U0 - s, U2 - v U0, (s-t)/2).
   template <int D, typename T>
-  __device__ __forceinline__ double speed(const T (&U)[NC]) const {
+  HWENO_HD void project(const Eig<T>& e, const T (&U)[NC], T (&w)[NC]) const {
+    if constexpr (DIM == 1) {
+      const T s = e.b2 * U[0] - e.b1 * (e.mu * U[1] - U[2]);
+      const T t = e.ic * (e.mu * U[0] - U[1]);
+      w[0] = T(0.5) * (s + t);
+      w[1] = U[0] - s;
+      w[2] = T(0.5) * (s - t);
+    } else {
+      const T s = e.b2 * U[0] - e.b1 * (e.mu * U[1] + e.nu * U[2] - U[3]);
+      const T t = D == 0 ? e.ic * (e.mu * U[0] - U[1]) : e.ic * (e.nu * U[0] - U[2]);
+      w[0] = T(0.5) * (s + t);
+      w[1] = U[0] - s;
+      w[2] = D == 0 ? U[2] - e.nu * U[0] : U[1] - e.mu * U[0];
+      w[3] = T(0.5) * (s - t);
+    }
+  }
+  template <int D, typename T>
+  HWENO_HD void unproject(const Eig<T>& e, const T (&c)[NC], T (&U)[NC]) const {
+    if constexpr (DIM == 1) {
+      const T a = c[0] + c[2], dd = c[2] - c[0];
+      const T s0 = a + c[1];
+      U[0] = s0;
+      U[1] = e.mu * s0 + e.c * dd;
+      U[2] = e.H * a + (e.mu * e.c) * dd + e.k * c[1];
+    } else {
+      const T a = c[0] + c[3], dd = c[3] - c[0];
+      const T s0 = a + c[1];
+      const T vn = D == 0 ? e.mu : e.nu, vt = D == 0 ? e.nu : e.mu;
+      U[0] = s0;
+      if (D == 0) {
+        U[1] = e.mu * s0 + e.c * dd;
+        U[2] = e.nu * s0 + c[2];
+      } else {
+        U[1] = e.mu * s0 + c[2];
+        U[2] = e.nu * s0 + e.c * dd;
+      }
+      U[3] = e.H * a + (vn * e.c) * dd + e.k * c[1] + vt * c[2];
+    }
+  }
+  template <int D, typename T>
+  HWENO_HD double speed(const T (&U)[NC]) const {
     const double r = (double)U[0];
     const double mu = (double)U[1] / r;
     const double nu = DIM == 2 ? (double)U[2] / r : 0.0;
@@ -331,7 +448,7 @@ struct Euler {
     return fabs(D == 0 ? mu : nu) + sqrt(gas * p / r);
   }
   template <typename T>
-  __device__ __forceinline__ unsigned admissible(const T (&U)[NC]) const {
+  HWENO_HD unsigned admissible(const T (&U)[NC]) const {
     unsigned f = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) f |= isfinite((double)U[c]) ? 0u : 1u;
@@ -349,7 +466,7 @@ struct Euler {
 // characteristic variable, project back (remarks on local characteristic
 // decomposition in sections 2 and 3). Scalar laws skip the projection.
 template <int D, class Sys, typename T>
-__device__ __forceinline__ void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
+HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
                                            const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
                                            const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
                                            const T (&Ap)[Sys::NC], T (&uR)[Sys::NC],
@@ -360,39 +477,26 @@ __device__ __forceinline__ void hweno_cell(const Sys& sy, const Scheme& s, doubl
   } else {
     const auto q = sy.prim(U0);
     const auto e = sy.eig(q);
+    T wm[NC], w0[NC], wp[NC], am[NC], ap[NC];
+    sy.template project<D>(e, Um, wm);
+    sy.template project<D>(e, U0, w0);
+    sy.template project<D>(e, Up, wp);
+    sy.template project<D>(e, Am, am);
+    sy.template project<D>(e, Ap, ap);
+    T cr[NC], cl[NC], ct[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) { uR[c] = T(0); uL[c] = T(0); at[c] = T(0); }
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      T l[NC];
-      sy.template left<D>(e, j, l);
-      T wm = T(0), w0 = T(0), wp = T(0), am = T(0), ap = T(0);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        wm += l[c] * Um[c];
-        w0 += l[c] * U0[c];
-        wp += l[c] * Up[c];
-        am += l[c] * Am[c];
-        ap += l[c] * Ap[c];
-      }
-      T cr, cl, ct;
-      hweno_point<T>(wm, w0, wp, am, ap, s, h, ih, cr, cl, ct);
-      T r[NC];
-      sy.template right<D>(e, j, r);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        uR[c] += r[c] * cr;
-        uL[c] += r[c] * cl;
-        at[c] += r[c] * ct;
-      }
-    }
+    for (int j = 0; j < NC; ++j)
+      hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, cr[j], cl[j], ct[j]);
+    sy.template unproject<D>(e, cr, uR);
+    sy.template unproject<D>(e, cl, uL);
+    sy.template unproject<D>(e, ct, at);
   }
 }
 
 // ------------------------------------------------------------- index maps
 // Ghost cells by index map: periodic wraps, transmissive clamps (copies the
 // nearest interior cell). Any integer i is accepted.
-__device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
+HWENO_HD int map_index(int i, int n, int lo, int hi) {
   if (i >= 0 && i < n) return i;
   const int side = i < 0 ? lo : hi;
   if (side == 0) {

@@ -54,9 +54,6 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
   for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
   return v;
 }
-template <typename T>
-__device__ __forceinline__ T from_next2(T x) { return __shfl_down(x, 2); }
-
 // Atomic max of non-negative doubles through their bit patterns (ordered
 // like unsigned integers); order-independent, hence deterministic.
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) {
@@ -246,6 +243,17 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) { Uc[c] = Un[c]; Vc[c] = Vn[c]; Wc[c] = Wn[c]; }
     if (r + 1 < y1 + 2) load_row<Sys>(A, r + 1, gcol, Un, Vn, Wn);  // prefetch
+    // RK base of this iteration's output row, loaded early to hide latency
+    T Bu[NC], Bv[NC], Bw[NC];
+    if (MODE >= kStage2 && r >= y0 + 2 && out_col) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int idx = c * A.plane + (r - 2) * A.nx + col;
+        Bu[c] = A.Ub[idx];
+        Bv[c] = A.Vb[idx];
+        Bw[c] = A.Wb[idx];
+      }
+    }
     // pointwise g, theta = g'(u) w, xi = g'(u) v of row r
     T gc[NC], tc[NC], xc[NC];
     {
@@ -302,9 +310,9 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
             const double Lv = RV[c] - ((double)Xn[c] - (double)Fx[c]) * s.idy;
             const double Lw = RW[c] - ((double)Tn[c] - (double)Ft[c]) * s.idy;
             const int idx = c * A.plane + o * A.nx + col;
-            const double ub = MODE >= kStage2 ? (double)A.Ub[idx] : 0.0;
-            const double vb = MODE >= kStage2 ? (double)A.Vb[idx] : 0.0;
-            const double wb = MODE >= kStage2 ? (double)A.Wb[idx] : 0.0;
+            const double ub = MODE >= kStage2 ? (double)Bu[c] : 0.0;
+            const double vb = MODE >= kStage2 ? (double)Bv[c] : 0.0;
+            const double wb = MODE >= kStage2 ? (double)Bw[c] : 0.0;
             Unew[c] = (T)rk<MODE>((double)Ua[c], ub, dt, Lu);
             A.Uo[idx] = Unew[c];
             A.Vo[idx] = (T)rk<MODE>((double)vt[c], vb, dt, Lv);
