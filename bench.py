@@ -114,6 +114,44 @@ def time_forward(n, precision, steps, warmup, seed=4000):
         sim_time=sim_t, state_finite=bool(torch.isfinite(U).all().item()))
 
 
+def time_adjoint(precision, n=512, steps=200, every=20):
+    """Adjoint workload: 2D Euler n x n periodic smooth data (seed 5000),
+    `steps` SSP-RK3 steps at the production dt of t = 0, checkpoints every
+    `every` steps; J = dx dy/2 sum (U_T - U*)^2 with U* the seed-5001 field.
+    Returns forward and backward (segment recompute + adjoint steps) wall
+    times of HwenoRollout."""
+    import torch
+    from paper_2411_11229_amd import hweno, rollout, workloads
+    w = workloads.euler2d_smooth(n, seed=5000)
+    tw = workloads.euler2d_smooth(n, seed=5001)
+    prob = hweno.Problem(**w.problem_kwargs(), precision=precision)
+    s = hweno.Solver(prob)
+    dt_ = prob.dtype
+    mk = lambda a: torch.tensor(a, dtype=dt_, device='cuda')
+    a0 = s.max_wavespeed(mk(w.U)).cpu()
+    dt_fixed = 0.6 / (float(a0[0]) / w.dx + float(a0[1]) / w.dy)
+    target = mk(tw.U)
+
+    def once(k):
+        X = [mk(a).requires_grad_(True) for a in (w.U, w.V, w.W)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = rollout.rollout(s, X[0], X[1], X[2], steps=k, rule='fixed', dt_fixed=dt_fixed,
+                              checkpoint_every=every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = 0.5 * ((out[0] - target) ** 2).sum() * w.dx * w.dy
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ok = all(bool(torch.isfinite(x.grad).all()) for x in X)
+        return t1 - t0, t2 - t1, ok
+
+    once(every)                       # warm-up
+    fwd, bwd, ok = once(steps)
+    return dict(forward_s=fwd, backward_s=bwd, ratio=bwd / fwd, grads_finite=ok)
+
+
 def cpu_baseline(n=512, steps=2, seed=4000):
     """The FP64 oracle (unchanged) on a bounded sample: the same four-quadrant
     generator at n x n, `steps` SSP-RK3 steps, one thread."""
@@ -171,6 +209,7 @@ def main():
     ap.add_argument('--n', type=int, default=2048)
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle baseline')
     ap.add_argument('--no-fp32', action='store_true', help='skip the FP32 form')
+    ap.add_argument('--no-adjoint', action='store_true', help='skip the adjoint/forward ratio')
     ap.add_argument('--probe', choices=['copy'], help='run a calibration probe instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
                     help='precision of the headline run')
@@ -196,6 +235,18 @@ def main():
         fp32 = dict(value=r['value'], ms_per_step=r['ms_per_step'],
                     avg_stage_kernel_ms=r['avg_stage_ms'], achieved_gbs=r['achieved_gbs'],
                     frac=r['achieved_gbs'] / HBM_PEAK_GBS)
+    adjoint = None
+    if not args.no_adjoint:
+        a64 = time_adjoint('f64')
+        a32 = time_adjoint('f32') if not args.no_fp32 else None
+        adjoint = dict(workload='2D Euler 512x512 periodic smooth (seed 5000), 200 SSP-RK3 steps at '
+                                'the t=0 production dt, checkpoints every 20, stage states stored '
+                                'during segment recompute',
+                       forward_s_f64=a64['forward_s'], backward_s_f64=a64['backward_s'],
+                       ratio_f64=a64['ratio'], grads_finite=a64['grads_finite'])
+        if a32:
+            adjoint.update(forward_s_f32=a32['forward_s'], backward_s_f32=a32['backward_s'],
+                           ratio_f32=a32['ratio'])
     cpu = None if args.no_cpu else cpu_baseline()
 
     traffic = traffic_record()
@@ -226,6 +277,7 @@ def main():
         'roofline': roof,
         'cpu_baseline': cpu,
         'fp32': fp32,
+        'adjoint_over_forward': adjoint,
         'sim_time_reached': main_run['sim_time'],
         'state_finite': main_run['state_finite'],
     }

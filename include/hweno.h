@@ -151,6 +151,16 @@ hweno_status hweno_step_profiled(const hweno_problem* prob, void* u, void* v, vo
                                  void* ws, hipStream_t stream, hipEvent_t* events);
 
 /*
+ * One SSP-RK3 step in place on (u, v, w) with a given time step (device
+ * double) and given stage alphas (device double[3][2], e.g. the alpha_rec
+ * of an earlier hweno_step): the map whose Jacobian hweno_adjoint_step
+ * transposes. No clipping, no time update. `stages` as in hweno_step.
+ */
+hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void* w,
+                               const double* dt, const double* alpha_rec, void* stages,
+                               void* ws, hipStream_t stream);
+
+/*
  * Discrete adjoint of one hweno_step (row a12 of the design: derived from
  * (fully-hweno)/(2Dfully-hweno)). Given lambda = dJ/dX^{n+1} (lam_*_in) it
  * writes dJ/dX^n (lam_*_out), where X = (u, v, w), with the recorded dt

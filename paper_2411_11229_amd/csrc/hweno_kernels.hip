@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "../../include/hweno.h"
+#include "hweno_adjoint.h"
 #include "hweno_device.h"
 
 namespace hweno {
@@ -474,6 +475,259 @@ __global__ void ws_init_kernel(StepScalars* sc) {
   sc->flags = 0u;
 }
 
+// ================================================================ adjoint
+// Vector-Jacobian product of one stage for one direction, on lines laid out
+// along memory rows (the y direction runs on transposed copies). Given the
+// state X = (u, a, o) -- a the derivative along the line, o the other one --
+// and cotangents a_B of B(X) = (u, a~, ...) and b of L(X), it writes
+//   G = (dB/dX)^T a_B + (dL_dir/dX)^T b
+// restricted to this direction's terms. Lanes hold "virtual" cells v =
+// 60 b - 4 + lane (ghost cells included), so every virtual cell in
+// [-2, n+2) is an output lane of exactly one block; contributions to ghost
+// cells go to a side buffer and are folded into their images by
+// ghost_fold_kernel (the transpose of the ghost index map).
+template <typename T>
+struct VjpArgs {
+  const T* X[3];          // u, along-derivative, other derivative (null in 1D)
+  const T* lam[3][3];     // cotangent sets [set][u, along, other]; null = zero
+  double ca[3], cb[3];    // a_B = sum ca_k lam_k, b = sum cb_k lam_k
+  int cb_dt;              // bit k set: cb_k is multiplied by *dt
+  const double* dt;
+  const double* alpha;    // [2]; this pass uses alpha[dir]
+  int dir;
+  int add_identity;       // add the u-part of a_B (B's u-component is the identity)
+  T* G[3];                // outputs (u, along, other), overwritten
+  T* ghost;               // [rows][4][3][NC] contributions of virtual cells -2, -1, n, n+1
+  int n, rows, plane;
+  int bc_lo, bc_hi;
+  double h, ih;
+  Scheme s;
+};
+
+template <class Sys, typename T, int D, int NF>
+__global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
+  constexpr int NC = Sys::NC;
+  using Bar = typename BarOf<Sys, T>::type;
+  const int lane = threadIdx.x;
+  const int row = blockIdx.y;
+  const int v = blockIdx.x * kXOut - 4 + lane;
+  const int g = map_index(v, A.n, A.bc_lo, A.bc_hi);
+  const bool interior = v >= 0 && v < A.n;
+  const bool out = lane >= kHalo && lane < kWave - kHalo && v >= -2 && v < A.n + 2;
+  const int base = row * A.n;
+  const double dtv = A.dt ? *A.dt : 0.0;
+  const T alpha = T(A.alpha[A.dir]);
+  const T h = T(A.h), ih = T(A.ih);
+  const Scheme& s = A.s;
+
+  T U[NC], Av[NC], Ov[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    U[c] = A.X[0][c * A.plane + base + g];
+    Av[c] = A.X[1][c * A.plane + base + g];
+    Ov[c] = NF == 3 ? A.X[2][c * A.plane + base + g] : T(0);
+  }
+  // cotangents; zero at ghost cells (L and B are defined on interior cells)
+  T aU[NC], aA[NC], bU[NC], bA[NC], bO[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) { aU[c] = T(0); aA[c] = T(0); bU[c] = T(0); bA[c] = T(0); bO[c] = T(0); }
+  if (interior) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T ck = T(A.ca[k]);
+      const T dk = T(A.cb[k] * (((A.cb_dt >> k) & 1) ? dtv : 1.0));
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int idx = c * A.plane + base + v;
+        const T lu = A.lam[k][0] ? A.lam[k][0][idx] : T(0);
+        const T la = A.lam[k][1] ? A.lam[k][1][idx] : T(0);
+        const T lo = (NF == 3 && A.lam[k][2]) ? A.lam[k][2][idx] : T(0);
+        aU[c] += ck * lu;
+        aA[c] += ck * la;
+        bU[c] += dk * lu;
+        bA[c] += dk * la;
+        bO[c] += dk * lo;
+      }
+    }
+  }
+  // ---- forward recompute of this cell's interface values
+  T Um[NC], Up[NC], Am[NC], Ap[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    Um[c] = from_prev(U[c]);
+    Up[c] = from_next(U[c]);
+    Am[c] = from_prev(Av[c]);
+    Ap[c] = from_next(Av[c]);
+  }
+  T uR[NC], uL[NC], at_[NC], vR[NC], vL[NC];
+  hweno_cell<D>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, uR, uL, at_);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Am[c], Ap[c], ih, vR[c], vL[c]);
+  // ---- interface cotangents: L_i = -(F_{i+1/2} - F_{i-1/2}) / h
+  T lF[NC], lH[NC], lE[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    lF[c] = (from_next(bU[c]) - bU[c]) * ih;
+    lH[c] = (from_next(bA[c]) - bA[c]) * ih;
+    lE[c] = NF == 3 ? (from_next(bO[c]) - bO[c]) * ih : T(0);
+  }
+  // ---- Lax-Friedrichs halves: minus side of x_{v+1/2} (uR, vR) and plus
+  // side of x_{v-1/2} (uL, vL)
+  T guR[NC], gvR[NC], guL[NC], gvL[NC];
+  {
+    T hF[NC], hH[NC], pF[NC], pH[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      hF[c] = T(0.5) * lF[c];
+      hH[c] = T(0.5) * lH[c];
+      pF[c] = T(0.5) * from_prev(lF[c]);
+      pH[c] = T(0.5) * from_prev(lH[c]);
+      guR[c] = alpha * hF[c];
+      gvR[c] = alpha * hH[c];
+      guL[c] = -alpha * pF[c];
+      gvL[c] = -alpha * pH[c];
+    }
+    const auto qr = sy.prim(uR);
+    Bar br{};
+    flux_vjp<D>(sy, uR, qr, hF, br, guR);
+    jac_vjp<D>(sy, uR, qr, vR, hH, br, guR, gvR);
+    prim_vjp(sy, uR, qr, br, guR);
+    const auto ql = sy.prim(uL);
+    Bar bl{};
+    flux_vjp<D>(sy, uL, ql, pF, bl, guL);
+    jac_vjp<D>(sy, uL, ql, vL, pH, bl, guL, gvL);
+    prim_vjp(sy, uL, ql, bl, guL);
+  }
+  // ---- central correction and mixed flux: gather from interfaces v-2..v+1
+  T gU[NC], gA[NC], gO[NC];
+  {
+    T gf[NC], gh[NC], ge[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T F1 = from_next(lF[c]), F0 = lF[c], Fm1 = from_prev(lF[c]), Fm2 = from_prev(Fm1);
+      const T H1 = from_next(lH[c]), H0 = lH[c], Hm1 = from_prev(lH[c]), Hm2 = from_prev(Hm1);
+      gf[c] = T(97.0 / 1920.0) * ((F0 + Fm1) - (F1 + Fm2)) +
+              ih * (T(697.0 / 5184.0) * (H1 - Hm2) + T(61.0 / 192.0) * (Hm1 - H0));
+      gh[c] = T(19.0 / 960.0) * h * (Fm2 - F1) + T(37.0 / 864.0) * (H1 + Hm2);
+      if constexpr (NF == 3) {
+        const T E1 = from_next(lE[c]), E0 = lE[c], Em1 = from_prev(lE[c]), Em2 = from_prev(Em1);
+        ge[c] = (T(7.0) * (E0 + Em1) - (E1 + Em2)) * T(1.0 / 12.0);
+      } else {
+        ge[c] = T(0);
+      }
+      gU[c] = T(0);
+      gA[c] = T(0);
+      gO[c] = T(0);
+    }
+    // pointwise f, f'(u) a, f'(u) o at the cell
+    const auto q = sy.prim(U);
+    Bar bq{};
+    flux_vjp<D>(sy, U, q, gf, bq, gU);
+    jac_vjp<D>(sy, U, q, Av, gh, bq, gU, gA);
+    if constexpr (NF == 3) jac_vjp<D>(sy, U, q, Ov, ge, bq, gU, gO);
+    prim_vjp(sy, U, q, bq, gU);
+  }
+  // ---- face derivatives and HWENO of this cell -> its stencil
+  T tm[NC], tc[NC], tp[NC], tAm[NC], tAp[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    tm[c] = T(0); tc[c] = T(0); tp[c] = T(0); tAm[c] = T(0); tAp[c] = T(0);
+    face_derivs_vjp(gvR[c], gvL[c], ih, tm[c], tc[c], tp[c], tAm[c], tAp[c]);
+  }
+  hweno_cell_vjp<D>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, guR, guL, aA, tm, tc, tp, tAm, tAp);
+  // ---- gather: own + right-neighbour part of the left lane + left part of the right lane
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    gU[c] += tc[c] + from_prev(tp[c]) + from_next(tm[c]);
+    gA[c] += from_prev(tAp[c]) + from_next(tAm[c]);
+    if (A.add_identity) gU[c] += aU[c];
+  }
+  if (out) {
+    if (interior) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int idx = c * A.plane + base + v;
+        A.G[0][idx] = gU[c];
+        A.G[1][idx] = gA[c];
+        if (NF == 3) A.G[2][idx] = gO[c];
+      }
+    } else {
+      const int slot = v < 0 ? v + 2 : v - A.n + 2;
+      T* gp = A.ghost + ((size_t)row * 4 + slot) * 3 * NC;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        gp[c] = gU[c];
+        gp[NC + c] = gA[c];
+        gp[2 * NC + c] = gO[c];
+      }
+    }
+  }
+}
+
+// Adds the ghost-cell contributions to the cells they were copied from, in a
+// fixed order (one thread per line, field and component).
+template <typename T>
+__global__ __launch_bounds__(256) void ghost_fold_kernel(T* G0, T* G1, T* G2, const T* ghost,
+                                                         int n, int rows, int plane, int nc,
+                                                         int nf, int bc_lo, int bc_hi) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = rows * nf * nc;
+  if (t >= total) return;
+  const int c = t % nc;
+  const int f = (t / nc) % nf;
+  const int row = t / (nc * nf);
+  T* G = f == 0 ? G0 : (f == 1 ? G1 : G2);
+  for (int slot = 0; slot < 4; ++slot) {
+    const int v = slot < 2 ? slot - 2 : n + slot - 2;
+    const int m = map_index(v, n, bc_lo, bc_hi);
+    G[c * plane + row * n + m] += ghost[((size_t)row * 4 + slot) * 3 * nc + f * nc + c];
+  }
+}
+
+// dst[p][x][y] (+)= sum_k coef_k src_k[p][y][x] for nplanes planes of
+// ny x nx; 32 x 32 tiles through LDS, coalesced on both sides.
+template <typename T>
+struct TArgs {
+  const T* src[3];
+  double coef[3];
+  int coef_dt;            // bit k: coef_k multiplied by *dt
+  const double* dt;
+  T* dst;
+  int accumulate;
+  int nx, ny, plane;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(TArgs<T> A) {
+  __shared__ T tile[32][33];
+  const int p = blockIdx.z;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const double dtv = A.dt ? *A.dt : 1.0;
+  T c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c[k] = T(A.coef[k] * (((A.coef_dt >> k) & 1) ? dtv : 1.0));
+  for (int j = threadIdx.y; j < 32; j += 8) {
+    const int x = x0 + threadIdx.x, y = y0 + j;
+    T val = T(0);
+    if (x < A.nx && y < A.ny) {
+      const int idx = p * A.plane + y * A.nx + x;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (A.src[k]) val += c[k] * A.src[k][idx];
+    }
+    tile[j][threadIdx.x] = val;
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += 8) {
+    const int y = y0 + threadIdx.x, x = x0 + j;
+    if (x < A.nx && y < A.ny) {
+      const int idx = p * A.plane + x * A.ny + y;
+      const T val = tile[threadIdx.x][j];
+      A.dst[idx] = A.accumulate ? A.dst[idx] + val : val;
+    }
+  }
+}
+
 }  // namespace hweno
 
 // =================================================================== host side
@@ -530,24 +784,38 @@ Geometry geometry(const hweno_problem* p) {
   return g;
 }
 
-// Workspace: scalars | per-block partial maxima | states.
+// Workspace: scalars | per-block partial maxima | states | adjoint scratch.
 // States are stored densely ([field][comp][ny][nx]); each region starts on a
 // 256-byte boundary. Regions: X^(1), X^(2), the RK base derivatives
-// (V~^n[, W~^n]) and three adjoint states.
+// (V~^n[, W~^n]), and for the adjoint: lambda^(2), lambda^(1), the transposed
+// state, the transposed cotangents (b, then a), the transposed y-pass
+// result, and the ghost-cell side buffer.
 struct WsLayout {
   StepScalars* sc;
   double* partial;
   char* x1;
   char* x2;
   char* base;
-  char* adj;
+  char* lam2;
+  char* lam1;
+  char* xt;
+  char* bt;
+  char* at;
+  char* gt;
+  char* ghost;
   size_t state_bytes;
 };
 
 size_t state_bytes(const Geometry& g) { return align_up((size_t)g.nf * g.nc * g.plane * g.esize, 256); }
 size_t base_bytes(const Geometry& g) { return align_up((size_t)(g.nf - 1) * g.nc * g.plane * g.esize, 256); }
-size_t ws_total(const Geometry& g) {
-  return kScalarBytes + kPartialBytes + 5 * state_bytes(g) + base_bytes(g);
+size_t comp_bytes(const Geometry& g) { return align_up((size_t)g.nc * g.plane * g.esize, 256); }
+size_t ghost_bytes(const hweno_problem* p, const Geometry& g) {
+  const size_t lines = (size_t)(p->nx > p->ny ? p->nx : p->ny);
+  return align_up(lines * 4 * 3 * g.nc * g.esize, 256);
+}
+size_t ws_total(const hweno_problem* p, const Geometry& g) {
+  return kScalarBytes + kPartialBytes + 4 * state_bytes(g) + base_bytes(g) +
+         (g.nf == 3 ? 3 * state_bytes(g) + comp_bytes(g) : 0) + ghost_bytes(p, g);
 }
 
 WsLayout ws_layout(void* ws, const Geometry& g) {
@@ -559,7 +827,19 @@ WsLayout ws_layout(void* ws, const Geometry& g) {
   w.x1 = b + kScalarBytes + kPartialBytes;
   w.x2 = w.x1 + w.state_bytes;
   w.base = w.x2 + w.state_bytes;
-  w.adj = w.base + base_bytes(g);
+  w.lam2 = w.base + base_bytes(g);
+  w.lam1 = w.lam2 + w.state_bytes;
+  char* nxt = w.lam1 + w.state_bytes;
+  if (g.nf == 3) {
+    w.xt = nxt;
+    w.bt = w.xt + w.state_bytes;
+    w.gt = w.bt + w.state_bytes;
+    w.at = w.gt + w.state_bytes;
+    nxt = w.at + comp_bytes(g);
+  } else {
+    w.xt = w.bt = w.gt = w.at = nullptr;
+  }
+  w.ghost = nxt;
   return w;
 }
 
@@ -654,6 +934,137 @@ hweno_status launch_speed_partial(const hweno_problem* p, const T* U, const Sys&
   return check_launch();
 }
 
+// One VJP of a stage: x-pass on the arrays as stored, and in 2D a y-pass on
+// transposed copies, whose result is transposed back and added.
+struct CotSet {
+  const void* f[3];       // u, v, w of one cotangent state (w null in 1D)
+  double ca, cb;
+  bool cb_dt;
+};
+
+template <class Sys, typename T, int DIM>
+hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g,
+                        const WsLayout& wl, const T* X[3], const CotSet* sets, int nsets,
+                        const double* alpha, const double* dt, T* out[3], hipStream_t st) {
+  constexpr int NC = Sys::NC;
+  const Scheme sc = make_scheme(p);
+  const int nx = p->nx, ny = p->ny, plane = nx * ny;
+  // x-pass
+  {
+    VjpArgs<T> A;
+    std::memset(&A, 0, sizeof(A));
+    for (int f = 0; f < 3; ++f) A.X[f] = X[f];
+    for (int k = 0; k < nsets; ++k) {
+      for (int f = 0; f < 3; ++f) A.lam[k][f] = (const T*)sets[k].f[f];
+      A.ca[k] = sets[k].ca;
+      A.cb[k] = sets[k].cb;
+      if (sets[k].cb_dt) A.cb_dt |= 1 << k;
+    }
+    A.dt = dt;
+    A.alpha = alpha;
+    A.dir = 0;
+    A.add_identity = 1;
+    for (int f = 0; f < 3; ++f) A.G[f] = out[f];
+    A.ghost = (T*)wl.ghost;
+    A.n = nx;
+    A.rows = ny;
+    A.plane = plane;
+    A.bc_lo = p->bc[0];
+    A.bc_hi = p->bc[1];
+    A.h = sc.dx;
+    A.ih = sc.idx;
+    A.s = sc;
+    dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
+    vjp_row_kernel<Sys, T, 0, DIM + 1><<<grid, kWave, 0, st>>>(A, sy);
+    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    const int tot = ny * g.nf * NC;
+    ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
+                                                           nx, ny, plane, NC, g.nf, p->bc[0], p->bc[1]);
+    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+  }
+  if constexpr (DIM == 2) {
+    const size_t cp = (size_t)NC * plane;
+    T* xt = (T*)wl.xt;
+    T* bt = (T*)wl.bt;
+    T* at = (T*)wl.at;
+    T* gt = (T*)wl.gt;
+    auto transpose = [&](const T* s0, const T* s1, const T* s2, const double c[3], int cdt, T* dst,
+                         int accumulate, int sx, int sy_) -> bool {
+      TArgs<T> t;
+      std::memset(&t, 0, sizeof(t));
+      t.src[0] = s0; t.src[1] = s1; t.src[2] = s2;
+      for (int k = 0; k < 3; ++k) t.coef[k] = c[k];
+      t.coef_dt = cdt;
+      t.dt = dt;
+      t.dst = dst;
+      t.accumulate = accumulate;
+      t.nx = sx;
+      t.ny = sy_;
+      t.plane = plane;
+      dim3 grid((sx + 31) / 32, (sy_ + 31) / 32, NC);
+      transpose_kernel<T><<<grid, dim3(32, 8), 0, st>>>(t);
+      return check_launch() == HWENO_OK;
+    };
+    const double one[3] = {1.0, 0.0, 0.0};
+    // state, with roles (u, along = w, other = v)
+    if (!transpose(X[0], nullptr, nullptr, one, 0, xt, 0, nx, ny)) return HWENO_EDEVICE;
+    if (!transpose(X[2], nullptr, nullptr, one, 0, xt + cp, 0, nx, ny)) return HWENO_EDEVICE;
+    if (!transpose(X[1], nullptr, nullptr, one, 0, xt + 2 * cp, 0, nx, ny)) return HWENO_EDEVICE;
+    // b (u, w, v roles) and the w-part of a_B
+    double cb[3] = {0, 0, 0}, ca[3] = {0, 0, 0};
+    int cdt = 0;
+    const T* lu[3] = {nullptr, nullptr, nullptr};
+    const T* lv[3] = {nullptr, nullptr, nullptr};
+    const T* lw[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < nsets; ++k) {
+      lu[k] = (const T*)sets[k].f[0];
+      lv[k] = (const T*)sets[k].f[1];
+      lw[k] = (const T*)sets[k].f[2];
+      cb[k] = sets[k].cb;
+      ca[k] = sets[k].ca;
+      if (sets[k].cb_dt) cdt |= 1 << k;
+    }
+    if (!transpose(lu[0], lu[1], lu[2], cb, cdt, bt, 0, nx, ny)) return HWENO_EDEVICE;
+    if (!transpose(lw[0], lw[1], lw[2], cb, cdt, bt + cp, 0, nx, ny)) return HWENO_EDEVICE;
+    if (!transpose(lv[0], lv[1], lv[2], cb, cdt, bt + 2 * cp, 0, nx, ny)) return HWENO_EDEVICE;
+    if (!transpose(lw[0], lw[1], lw[2], ca, 0, at, 0, nx, ny)) return HWENO_EDEVICE;
+    // y-pass on the transposed lines (length ny, nx of them)
+    VjpArgs<T> A;
+    std::memset(&A, 0, sizeof(A));
+    A.X[0] = xt; A.X[1] = xt + cp; A.X[2] = xt + 2 * cp;
+    A.lam[0][0] = bt; A.lam[0][1] = bt + cp; A.lam[0][2] = bt + 2 * cp;
+    A.ca[0] = 0.0; A.cb[0] = 1.0;
+    A.lam[1][1] = at;
+    A.ca[1] = 1.0; A.cb[1] = 0.0;
+    A.dt = dt;
+    A.alpha = alpha;
+    A.dir = 1;
+    A.add_identity = 0;
+    A.G[0] = gt; A.G[1] = gt + cp; A.G[2] = gt + 2 * cp;
+    A.ghost = (T*)wl.ghost;
+    A.n = ny;
+    A.rows = nx;
+    A.plane = plane;
+    A.bc_lo = p->bc[2];
+    A.bc_hi = p->bc[3];
+    A.h = sc.dy;
+    A.ih = sc.idy;
+    A.s = sc;
+    dim3 grid((ny + 4 + kXOut - 1) / kXOut, nx);
+    vjp_row_kernel<Sys, T, 1, 3><<<grid, kWave, 0, st>>>(A, sy);
+    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    const int tot = nx * 3 * NC;
+    ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(gt, gt + cp, gt + 2 * cp, (const T*)wl.ghost,
+                                                           ny, nx, plane, NC, 3, p->bc[2], p->bc[3]);
+    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    // back: u += gt_u^T, w += gt_along^T, v += gt_other^T
+    if (!transpose(gt, nullptr, nullptr, one, 0, out[0], 1, ny, nx)) return HWENO_EDEVICE;
+    if (!transpose(gt + cp, nullptr, nullptr, one, 0, out[2], 1, ny, nx)) return HWENO_EDEVICE;
+    if (!transpose(gt + 2 * cp, nullptr, nullptr, one, 0, out[1], 1, ny, nx)) return HWENO_EDEVICE;
+  }
+  return HWENO_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -676,7 +1087,7 @@ hweno_status hweno_workspace_bytes(const hweno_problem* p, size_t* bytes) {
   if (st != HWENO_OK) return st;
   if (!bytes) return HWENO_EINVAL;
   const Geometry g = geometry(p);
-  *bytes = ws_total(g);
+  *bytes = ws_total(p, g);
   return HWENO_OK;
 }
 
@@ -825,13 +1236,113 @@ hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void*
   });
 }
 
-hweno_status hweno_adjoint_step(const hweno_problem* p, const void*, const void*, const void*,
-                                const void*, const double*, const double*, const void*,
-                                const void*, const void*, void*, void*, void*, void*,
-                                hipStream_t) {
+hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w, const double* dt,
+                               const double* alpha_rec, void* stages, void* ws, hipStream_t stream) {
   hweno_status st = validate(p);
   if (st != HWENO_OK) return st;
-  return HWENO_EUNSUPPORTED;
+  if (!u || !v || !dt || !alpha_rec || !ws) return HWENO_EINVAL;
+  if (p->dim == 2 && !w) return HWENO_EINVAL;
+  if (p->dim == 1 && w) return HWENO_EINVAL;
+  const Geometry g = geometry(p);
+  WsLayout wl = ws_layout(ws, g);
+  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
+    using T = decltype(tag);
+    using Sys = decltype(sy);
+    constexpr int DIM = decltype(dimc)::value;
+    const size_t fs = (size_t)g.nc * g.plane;
+    char* x1 = stages ? (char*)stages : wl.x1;
+    char* x2 = stages ? (char*)stages + (size_t)g.nf * fs * sizeof(T) : wl.x2;
+    auto F = [&](char* b, int f) { return (T*)(b + (size_t)f * fs * sizeof(T)); };
+    T* Vt = (T*)wl.base;
+    T* Wt = DIM == 2 ? Vt + fs : nullptr;
+    StageArgs<T> A = base_args<T>(p);
+    A.dt = dt;
+    hweno_status s2;
+    A.U = (const T*)u; A.V = (const T*)v; A.W = (const T*)w;
+    A.Uo = F(x1, 0); A.Vo = F(x1, 1); A.Wo = DIM == 2 ? F(x1, 2) : nullptr;
+    A.Vt = Vt; A.Wt = Wt;
+    A.alpha = alpha_rec;
+    if ((s2 = launch_stage<Sys, T, DIM>(kStage1, A, sy, stream)) != HWENO_OK) return s2;
+    A.U = F(x1, 0); A.V = F(x1, 1); A.W = DIM == 2 ? F(x1, 2) : nullptr;
+    A.Ub = (const T*)u; A.Vb = Vt; A.Wb = Wt;
+    A.Uo = F(x2, 0); A.Vo = F(x2, 1); A.Wo = DIM == 2 ? F(x2, 2) : nullptr;
+    A.Vt = nullptr; A.Wt = nullptr;
+    A.alpha = alpha_rec + 2;
+    if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
+    A.U = F(x2, 0); A.V = F(x2, 1); A.W = DIM == 2 ? F(x2, 2) : nullptr;
+    A.Uo = (T*)u; A.Vo = (T*)v; A.Wo = (T*)w;
+    A.alpha = alpha_rec + 4;
+    return launch_stage<Sys, T, DIM>(kStage3, A, sy, stream);
+  });
+}
+
+hweno_status hweno_adjoint_step(const hweno_problem* p, const void* u_n, const void* v_n,
+                                const void* w_n, const void* stages, const double* dt,
+                                const double* alpha_rec, const void* lam_u_in,
+                                const void* lam_v_in, const void* lam_w_in, void* lam_u_out,
+                                void* lam_v_out, void* lam_w_out, void* ws, hipStream_t stream) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  const bool two = p->dim == 2;
+  if (!u_n || !v_n || !dt || !alpha_rec || !lam_u_in || !lam_v_in || !lam_u_out || !lam_v_out || !ws)
+    return HWENO_EINVAL;
+  if (two && (!w_n || !lam_w_in || !lam_w_out)) return HWENO_EINVAL;
+  if (!two && (w_n || lam_w_in || lam_w_out)) return HWENO_EINVAL;
+  const void* ins[8] = {u_n, v_n, w_n, stages, lam_u_in, lam_v_in, lam_w_in, nullptr};
+  void* outs[3] = {lam_u_out, lam_v_out, lam_w_out};
+  for (auto o : outs)
+    for (auto i : ins)
+      if (o && i && o == i) return HWENO_EINVAL;
+  const Geometry g = geometry(p);
+  WsLayout wl = ws_layout(ws, g);
+  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
+    using T = decltype(tag);
+    using Sys = decltype(sy);
+    constexpr int DIM = decltype(dimc)::value;
+    const size_t P = g.plane;
+    const size_t fs = (size_t)g.nc * P;        // elements per field
+    char* x1 = stages ? (char*)stages : wl.x1;
+    char* x2 = stages ? (char*)stages + (size_t)g.nf * fs * sizeof(T) : wl.x2;
+    auto F = [&](char* b, int f) { return (T*)(b + (size_t)f * fs * sizeof(T)); };
+    hweno_status s2;
+    if (!stages) {
+      // recompute X^(1), X^(2) with the recorded alphas and dt
+      T* Vt = (T*)wl.base;
+      T* Wt = DIM == 2 ? Vt + fs : nullptr;
+      StageArgs<T> A = base_args<T>(p);
+      A.dt = dt;
+      A.U = (const T*)u_n; A.V = (const T*)v_n; A.W = (const T*)w_n;
+      A.Uo = F(x1, 0); A.Vo = F(x1, 1); A.Wo = DIM == 2 ? F(x1, 2) : nullptr;
+      A.Vt = Vt; A.Wt = Wt;
+      A.alpha = alpha_rec;
+      if ((s2 = launch_stage<Sys, T, DIM>(kStage1, A, sy, stream)) != HWENO_OK) return s2;
+      A.U = F(x1, 0); A.V = F(x1, 1); A.W = DIM == 2 ? F(x1, 2) : nullptr;
+      A.Ub = (const T*)u_n; A.Vb = Vt; A.Wb = Wt;
+      A.Uo = F(x2, 0); A.Vo = F(x2, 1); A.Wo = DIM == 2 ? F(x2, 2) : nullptr;
+      A.Vt = nullptr; A.Wt = nullptr;
+      A.alpha = alpha_rec + 2;
+      if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
+    }
+    T* l2[3] = {F(wl.lam2, 0), F(wl.lam2, 1), DIM == 2 ? F(wl.lam2, 2) : nullptr};
+    T* l1[3] = {F(wl.lam1, 0), F(wl.lam1, 1), DIM == 2 ? F(wl.lam1, 2) : nullptr};
+    T* lo[3] = {(T*)lam_u_out, (T*)lam_v_out, (T*)lam_w_out};
+    const T* X2[3] = {F(x2, 0), F(x2, 1), DIM == 2 ? F(x2, 2) : nullptr};
+    const T* X1[3] = {F(x1, 0), F(x1, 1), DIM == 2 ? F(x1, 2) : nullptr};
+    const T* X0[3] = {(const T*)u_n, (const T*)v_n, (const T*)w_n};
+    // lambda^(2) = vjp(X^(2); 2/3 lambda, 2/3 dt lambda)
+    CotSet s3 = {{lam_u_in, lam_v_in, lam_w_in}, 2.0 / 3.0, 2.0 / 3.0, true};
+    if ((s2 = launch_vjp<Sys, T, DIM>(p, sy, g, wl, X2, &s3, 1, alpha_rec + 4, dt, l2, stream)) != HWENO_OK)
+      return s2;
+    // lambda^(1) = vjp(X^(1); 1/4 lambda^(2), 1/4 dt lambda^(2))
+    CotSet s22 = {{l2[0], l2[1], l2[2]}, 0.25, 0.25, true};
+    if ((s2 = launch_vjp<Sys, T, DIM>(p, sy, g, wl, X1, &s22, 1, alpha_rec + 2, dt, l1, stream)) != HWENO_OK)
+      return s2;
+    // lambda^n = vjp(X^n; lambda^(1) + 3/4 lambda^(2) + 1/3 lambda, dt lambda^(1))
+    CotSet s1[3] = {{{l1[0], l1[1], l1[2]}, 1.0, 1.0, true},
+                    {{l2[0], l2[1], l2[2]}, 0.75, 0.0, false},
+                    {{lam_u_in, lam_v_in, lam_w_in}, 1.0 / 3.0, 0.0, false}};
+    return launch_vjp<Sys, T, DIM>(p, sy, g, wl, X0, s1, 3, alpha_rec, dt, lo, stream);
+  });
 }
 
 hweno_status hweno_health(const hweno_problem* p, void* ws, hipStream_t stream, int32_t clear) {

@@ -52,6 +52,7 @@ _SIGS = {
     'hweno_step_profiled': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P],
                             ctypes.c_int),
+    'hweno_step_frozen': ([ctypes.POINTER(_CProblem)] + [_P] * 8, ctypes.c_int),
     'hweno_adjoint_step': ([ctypes.POINTER(_CProblem)] + [_P] * 14, ctypes.c_int),
     'hweno_health': ([ctypes.POINTER(_CProblem), _P, _P, ctypes.c_int32], ctypes.c_int),
 }
@@ -226,11 +227,44 @@ class Solver:
         else:
             _check(self.lib.hweno_step_profiled(*args, events), 'hweno_step_profiled')
 
+    def _stages_ok(self, stages):
+        if stages is None:
+            return None
+        nf = 3 if self.prob.dim == 2 else 2
+        need = 2 * nf * self.prob.ncomp * self.prob.nx * self.prob.ny
+        if not (isinstance(stages, torch.Tensor) and stages.dtype == self.prob.dtype
+                and stages.numel() >= need and stages.is_contiguous()
+                and stages.device.type == 'cuda'):
+            raise ValueError('stages: wrong dtype, size or layout')
+        return stages
+
+    def _scalars_ok(self, dt, alpha_rec):
+        for name, x, n in (('dt', dt, 1), ('alpha_rec', alpha_rec, 6)):
+            if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.numel() >= n
+                    and x.is_contiguous() and x.device.type == 'cuda'):
+                raise ValueError(f'{name} must be a contiguous float64 device tensor')
+
+    def step_frozen(self, U, V, W, dt, alpha_rec, stages=None):
+        """One step in place with the given dt (device, 1 value) and stage
+        alphas (device, 6 values): the map the adjoint differentiates."""
+        two = self.prob.dim == 2
+        U, V = self._state(U, 'U'), self._state(V, 'V')
+        W = self._state(W, 'W') if two else None
+        self._scalars_ok(dt, alpha_rec)
+        _check(self.lib.hweno_step_frozen(ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W),
+                                          _ptr(dt), _ptr(alpha_rec), _ptr(self._stages_ok(stages)),
+                                          _ptr(self.ws), _stream(self.device)), 'hweno_step_frozen')
+
     def adjoint_step(self, U, V, W, dt, alpha_rec, lam_in, lam_out, stages=None):
         """dJ/dX^n into ``lam_out`` (3-tuple, or 2-tuple in 1D) from dJ/dX^{n+1}."""
         two = self.prob.dim == 2
-        li = list(lam_in) + [None] * (3 - len(lam_in))
-        lo = list(lam_out) + [None] * (3 - len(lam_out))
+        U, V = self._state(U, 'U'), self._state(V, 'V')
+        W = self._state(W, 'W') if two else None
+        self._scalars_ok(dt, alpha_rec)
+        nf = 3 if two else 2
+        li = [self._state(x, 'lam_in') for x in list(lam_in)[:nf]] + [None] * (3 - nf)
+        lo = [self._state(x, 'lam_out') for x in list(lam_out)[:nf]] + [None] * (3 - nf)
+        stages = self._stages_ok(stages)
         _check(self.lib.hweno_adjoint_step(
             ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W if two else None), _ptr(stages),
             _ptr(dt), _ptr(alpha_rec), _ptr(li[0]), _ptr(li[1]), _ptr(li[2] if two else None),

@@ -1,0 +1,76 @@
+"""Differentiable rollout of the HWENO-I time stepping (torch.autograd).
+
+``HwenoRollout.apply(U0, V0, W0, solver, steps, ...)`` runs ``steps``
+SSP-RK3 steps on the GPU and returns the final (U, V, W) (or (U, V) in 1D).
+Its backward applies the hand-written discrete adjoint of each step
+(``hweno_adjoint_step``) in reverse order, with the Lax-Friedrichs alphas and
+time steps recorded by the forward held fixed. Memory: the forward keeps a
+checkpoint of the state every ``checkpoint_every`` steps; the backward re-runs
+one segment at a time from its checkpoint with the recorded dt and alphas
+(``hweno_step_frozen``), keeping that segment's step-start states and, by
+default, its stage states X^(1), X^(2), so the adjoint of a step needs no
+forward recomputation.
+"""
+import torch
+
+from . import hweno
+
+
+class HwenoRollout(torch.autograd.Function):
+
+    @staticmethod
+    def forward(ctx, U0, V0, W0, solver, steps, rule='production', cfl=0.6, dt_fixed=0.0,
+                checkpoint_every=20, store_stages=True):
+        two = solver.prob.dim == 2
+        dev = solver.device
+        U = U0.detach().clone().contiguous()
+        V = V0.detach().clone().contiguous()
+        W = W0.detach().clone().contiguous() if two else None
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        dts = torch.zeros(steps, dtype=torch.float64, device=dev)
+        recs = torch.zeros(steps, 6, dtype=torch.float64, device=dev)
+        ckpts = []
+        for k in range(steps):
+            if k % checkpoint_every == 0:
+                ckpts.append((U.clone(), V.clone(), W.clone() if two else None))
+            solver.step(U, V, W, t, float('inf'), rule, cfl, dt_fixed,
+                        dt_used=dts[k:k + 1], alpha_rec=recs[k])
+        ctx.solver, ctx.steps, ctx.every = solver, steps, checkpoint_every
+        ctx.ckpts, ctx.dts, ctx.recs, ctx.two = ckpts, dts, recs, two
+        ctx.store_stages = store_stages
+        return (U, V, W) if two else (U, V)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        s, two, every = ctx.solver, ctx.two, ctx.every
+        nf = 3 if two else 2
+        lam = [g.contiguous().clone() if g is not None else torch.zeros(s.prob.shape, dtype=s.prob.dtype,
+                                                                        device=s.device)
+               for g in grads[:nf]]
+        out = [s.new_state() for _ in range(nf)]
+        per_stage = 2 * nf * s.prob.ncomp * s.prob.nx * s.prob.ny
+        stage_buf = (torch.empty(every, per_stage, dtype=s.prob.dtype, device=s.device)
+                     if ctx.store_stages else None)
+        for seg, start in reversed(list(enumerate(range(0, ctx.steps, every)))):
+            end = min(start + every, ctx.steps)
+            U, V, W = (x.clone() if x is not None else None for x in ctx.ckpts[seg])
+            starts = []
+            for k in range(start, end):
+                starts.append((U.clone(), V.clone(), W.clone() if two else None))
+                st = stage_buf[k - start] if stage_buf is not None else None
+                s.step_frozen(U, V, W, ctx.dts[k:k + 1], ctx.recs[k], stages=st)
+            for k in reversed(range(start, end)):
+                Xk = starts[k - start]
+                st = stage_buf[k - start] if stage_buf is not None else None
+                s.adjoint_step(Xk[0], Xk[1], Xk[2], ctx.dts[k:k + 1], ctx.recs[k], lam, out, stages=st)
+                lam, out = out, lam
+        gU, gV = lam[0], lam[1]
+        gW = lam[2] if two else None
+        return gU, gV, gW, None, None, None, None, None, None, None
+
+
+def rollout(solver, U0, V0, W0=None, steps=1, rule='production', cfl=0.6, dt_fixed=0.0,
+            checkpoint_every=20, store_stages=True):
+    """Functional form of HwenoRollout.apply."""
+    return HwenoRollout.apply(U0, V0, W0, solver, steps, rule, cfl, dt_fixed, checkpoint_every,
+                              store_stages)
