@@ -116,29 +116,35 @@ HWENO_HD float rsqrt_nr(float x) {
 //   vt = the modified derivative at x_i    -- (limiter),
 // sharing one set of smoothness indicators (GHYZ) between the three.
 //
-// With the normalised weights w_l = lin_l (1 + r_l) / S, r_l = tau/(beta_l +
-// eps), the combination of (interp) is rewritten as
-//   [ (1+r0) (p0 - g1 (p1 + p2)) + g1 ((1+r1) p1 + (1+r2) p2) ] / S,
-// which needs gamma1 = gamma2 (the paper's choice). The three ratios share
-// one division, and both normalisations share another.
+// Arithmetic: with r_l = tau/(beta_l + eps), o_l = 1 + r_l, the normalised
+// weights are w_l = lin_l o_l / S, S = gamma0 o0 + g1 (o1 + o2) (gamma1 =
+// gamma2 = g1, the paper's choice). Written through the one-sided
+// differences e1 = u_i - u_{i-1}, e2 = u_{i+1} - u_i, the candidates are
+// p1 = u_i + e1/2, p2 = u_i + e2/2 and p0 = u_i + e1/8 + 9e2/16 -
+// dx(3v_{i-1} + 9v_{i+1})/64; the u_i terms of (interp) add up to u_i S, so
+//   u^-_{i+1/2} = u_i + [o0 B_R + (g1/2) X] / S,
+//   u^+_{i-1/2} = u_i - [o0 B_L + (g1/2) X] / S,
+//   v~_i        = [o0 ((3/4 - d1)(e1 + e2)/dx - (v_{i-1} + v_{i+1})/4) + d1 X/dx] / S_d,
+// with X = o1 e1 + o2 e2, B_R = k1 e1 + k2 e2 - dx(3v_{i-1} + 9v_{i+1})/64,
+// B_L = k2 e1 + k1 e2 - dx(9v_{i-1} + 3v_{i+1})/64, k1 = 1/8 - g1/2,
+// k2 = 9/16 - g1/2 and S_d = d0 o0 + d1 (o1 + o2). The three ratios share one
+// division, both normalisations another.
 template <typename T>
 HWENO_HD void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
                                             double h, double ih, T& uR, T& uL, T& vt) {
-  const double dm = (double)um, dc = (double)u0, dp = (double)up;
-  const double sv = 0.25 * h * ((double)vm + (double)vp);
-  const double dv = 0.25 * h * ((double)vm - (double)vp);
-  const double cdf = dp - dm;                 // u_{i+1} - u_{i-1}
-  const double sdf = dm - 2.0 * dc + dp;      // u_{i-1} - 2u_i + u_{i+1}
-  // (GHYZ) closed form: a1..a4 and beta0; beta1, beta2
-  const double a1 = 0.75 * cdf - sv;
-  const double a2 = sdf + dv;
+  const double dc = (double)u0;
+  const double e1 = dc - (double)um, e2 = (double)up - dc;
+  const double vmd = (double)vm, vpd = (double)vp;
+  const double hvm = h * vmd, hvp = h * vpd;
+  // (GHYZ) closed form: cdf = u_{i+1} - u_{i-1}, sdf = u_{i-1} - 2u_i + u_{i+1}
+  const double cdf = e1 + e2, sdf = e2 - e1;
+  const double sv = 0.25 * (hvm + hvp), dv = 0.25 * (hvm - hvp);
   const double a3 = sv - 0.25 * cdf;
   const double a4 = -0.5 * sdf - dv;
-  const double t1 = a1 + 0.25 * a3;
-  const double t2 = a2 + (63.0 / 130.0) * a4;
+  const double t1 = 0.6875 * cdf - 0.75 * sv;                     // a1 + a3/4
+  const double t2 = (197.0 / 260.0) * sdf + (67.0 / 130.0) * dv;  // a2 + 63/130 a4
   const double b0 = t1 * t1 + (13.0 / 3.0) * t2 * t2 + (781.0 / 20.0) * a3 * a3 +
                     (1421461.0 / 2275.0) * a4 * a4;
-  const double e1 = dc - dm, e2 = dp - dc;
   const double b1 = e1 * e1, b2 = e2 * e2;
   // (nonlinear)
   const double ts = fabs(b0 - b1) + fabs(b0 - b2);
@@ -149,26 +155,21 @@ HWENO_HD void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
   const double o0 = 1.0 + ti * q12;           // 1 + tau/(beta0+eps)
   const double o1 = 1.0 + ti * (q0 * q2);     // 1 + tau/(beta1+eps)
   const double o2 = 1.0 + ti * (q0 * q1);     // 1 + tau/(beta2+eps)
-  const double Sg = s.gamma0 * o0 + s.g1 * (o1 + o2);
-  const double Sd = s.d0 * o0 + s.d1 * (o1 + o2);
+  const double o12 = o1 + o2;
+  const double Sg = s.gamma0 * o0 + s.g1 * o12;
+  const double Sd = s.d0 * o0 + s.d1 * o12;
   const double inv = rcp_nr(Sg * Sd);
   const double iSg = Sd * inv, iSd = Sg * inv;
-  // (Pxi): candidates at x_{i+1/2}
-  const double vmd = (double)vm, vpd = (double)vp;
-  const double P0 = -0.125 * dm + 0.5625 * (dc + dp) - h * (0.046875 * vmd + 0.140625 * vpd);
-  const double P1 = -0.5 * dm + 1.5 * dc;
-  const double P2 = 0.5 * (dc + dp);
-  // mirror image: candidates at x_{i-1/2}; Q1 lives on {i, i+1}, Q2 on {i-1, i}
-  const double Q0 = -0.125 * dp + 0.5625 * (dc + dm) + h * (0.046875 * vpd + 0.140625 * vmd);
-  const double Q1 = -0.5 * dp + 1.5 * dc;
-  const double Q2 = 0.5 * (dc + dm);
-  // (limiter-p): candidate derivatives at x_i
-  const double D0 = 0.75 * ih * cdf - 0.25 * (vmd + vpd);
-  const double D1 = ih * e1;
-  const double D2 = ih * e2;
-  uR = (T)((o0 * (P0 - s.g1 * (P1 + P2)) + s.g1 * (o1 * P1 + o2 * P2)) * iSg);
-  uL = (T)((o0 * (Q0 - s.g1 * (Q1 + Q2)) + s.g1 * (o2 * Q1 + o1 * Q2)) * iSg);
-  vt = (T)((o0 * (D0 - s.d1 * (D1 + D2)) + s.d1 * (o1 * D1 + o2 * D2)) * iSd);
+  // (Pxi), its mirror image and (limiter-p), combined as above
+  const double X = o1 * e1 + o2 * e2;
+  const double gX = 0.5 * s.g1 * X;
+  const double k1 = 0.125 - 0.5 * s.g1, k2 = 0.5625 - 0.5 * s.g1;
+  const double BR = k1 * e1 + k2 * e2 - (0.046875 * hvm + 0.140625 * hvp);
+  const double BL = k2 * e1 + k1 * e2 - (0.140625 * hvm + 0.046875 * hvp);
+  uR = (T)(dc + (o0 * BR + gX) * iSg);
+  uL = (T)(dc - (o0 * BL + gX) * iSg);
+  const double AT = (0.75 - s.d1) * ih * cdf - 0.25 * (vmd + vpd);
+  vt = (T)((o0 * AT + s.d1 * ih * X) * iSd);
 }
 
 // (P'xi) and its mirror: v^-_{i+1/2} = p0'(x_{i+1/2}), v^+_{i-1/2} = p0'(x_{i-1/2}).
@@ -228,6 +229,13 @@ struct Advection {
   HWENO_HD unsigned admissible(const T (&U)[NC]) const {
     return isfinite((double)U[0]) ? 0u : 1u;
   }
+  // spectral radii in x and y, and the admissibility flags, in one pass
+  template <typename T>
+  HWENO_HD unsigned speeds(const T (&U)[NC], double& sx, double& sy) const {
+    sx = fabs(a);
+    sy = fabs(b);
+    return admissible(U);
+  }
 };
 
 struct Burgers {
@@ -250,6 +258,11 @@ struct Burgers {
   template <typename T>
   HWENO_HD unsigned admissible(const T (&U)[NC]) const {
     return isfinite((double)U[0]) ? 0u : 1u;
+  }
+  template <typename T>
+  HWENO_HD unsigned speeds(const T (&U)[NC], double& sx, double& sy) const {
+    sx = sy = fabs((double)U[0]);
+    return admissible(U);
   }
 };
 
@@ -447,6 +460,25 @@ struct Euler {
     const double p = (gas - 1.0) * ((double)U[E_] - 0.5 * r * (mu * mu + nu * nu));
     return fabs(D == 0 ? mu : nu) + sqrt(gas * p / r);
   }
+  // |u| + c and |v| + c with the admissibility flags, in one pass (Newton-
+  // refined reciprocal and inverse square root).
+  template <typename T>
+  HWENO_HD unsigned speeds(const T (&U)[NC], double& sx, double& sy) const {
+    const double r = (double)U[0];
+    const double ir = rcp_nr(r);
+    const double mu = (double)U[1] * ir;
+    const double nu = DIM == 2 ? (double)U[2] * ir : 0.0;
+    const double p = (gas - 1.0) * ((double)U[E_] - 0.5 * r * (mu * mu + nu * nu));
+    const double c2 = gas * p * ir;
+    const double c = c2 * rsqrt_nr(c2);
+    sx = fabs(mu) + c;
+    sy = fabs(nu) + c;
+    unsigned f = 0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) f |= isfinite((double)U[k]) ? 0u : 1u;
+    if (!(r > 0.0) || !(p > 0.0)) f |= 2u;
+    return f;
+  }
   template <typename T>
   HWENO_HD unsigned admissible(const T (&U)[NC]) const {
     unsigned f = 0;
@@ -466,7 +498,8 @@ struct Euler {
 // characteristic variable, project back (remarks on local characteristic
 // decomposition in sections 2 and 3). Scalar laws skip the projection.
 template <int D, class Sys, typename T>
-HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
+HWENO_HD void hweno_cell_q(const Sys& sy, const Scheme& s, double h, double ih,
+                           const typename Sys::template Prim<T>& q,
                                            const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
                                            const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
                                            const T (&Ap)[Sys::NC], T (&uR)[Sys::NC],
@@ -475,7 +508,6 @@ HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
   if constexpr (!Sys::kChar) {
     hweno_point<T>(Um[0], U0[0], Up[0], Am[0], Ap[0], s, h, ih, uR[0], uL[0], at[0]);
   } else {
-    const auto q = sy.prim(U0);
     const auto e = sy.eig(q);
     T wm[NC], w0[NC], wp[NC], am[NC], ap[NC];
     sy.template project<D>(e, Um, wm);
@@ -491,6 +523,15 @@ HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
     sy.template unproject<D>(e, cl, uL);
     sy.template unproject<D>(e, ct, at);
   }
+}
+
+// The same, computing the centre's primitive quantities itself.
+template <int D, class Sys, typename T>
+HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
+                         const T (&Um)[Sys::NC], const T (&U0)[Sys::NC], const T (&Up)[Sys::NC],
+                         const T (&Am)[Sys::NC], const T (&Ap)[Sys::NC], T (&uR)[Sys::NC],
+                         T (&uL)[Sys::NC], T (&at)[Sys::NC]) {
+  hweno_cell_q<D>(sy, s, h, ih, sy.prim(U0), Um, U0, Up, Am, Ap, uR, uL, at);
 }
 
 // ------------------------------------------------------------- index maps

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <atomic>
 #include <cstring>
 #include <type_traits>
 
@@ -85,13 +86,13 @@ __device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, double a
   }
   // Step 1: HWENO once per cell -> u at both faces, v~ at the centre
   T uR[NC], uL[NC], vR[NC], vL[NC];
-  hweno_cell<0>(sy, s, s.dx, s.idx, Um, U, Up, Vm, Vp, uR, uL, vt);
+  const auto q = sy.prim(U);
+  hweno_cell_q<0>(sy, s, s.dx, s.idx, q, Um, U, Up, Vm, Vp, uR, uL, vt);
 #pragma unroll
   for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Vm[c], Vp[c], ih, vR[c], vL[c]);
   // pointwise f, h = f'(u) v, eta = f'(u) w at the cell centre
   T f[NC], hf[NC], e[NC];
   {
-    const auto q = sy.prim(U);
     sy.template flux<0>(U, q, f);
     sy.template jac<0>(U, q, V, hf);
     if constexpr (NF == 3) sy.template jac<0>(U, q, W, e);
@@ -182,8 +183,8 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
       if (MODE == kStage1 || MODE == kRhs) A.Vt[o] = vt[c];
     }
     if (A.alpha_next) {
-      smax = sy.template speed<0>(Un);
-      flag = sy.admissible(Un);
+      double sy_;
+      flag = sy.speeds(Un, smax, sy_);
     }
   }
   if (A.alpha_next) {
@@ -231,8 +232,12 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
 
   // register ring over rows (a = r-2, b = r-1 at the top of iteration r)
   T Ua[NC], Ub[NC], Va[NC], Vb[NC], Wa[NC], Wb[NC];
-  T g3[NC], g2[NC], g1[NC], t3[NC], t2[NC], t1[NC], x3[NC], x2[NC], x1[NC];
-  T mGa[NC], mTa[NC], wta[NC];        // top-face LF halves and w~ of row r-2
+  // the pointwise y-fluxes g, theta, xi of rows r-3, r-2, r-1 live in LDS,
+  // slot (row mod 3); each lane only touches its own column
+  __shared__ T ring[3][3][NC][kWave];
+  int slot = ((y0 - 2) % 3 + 3) % 3;   // slot of row r (and of row r-3)
+  // top-face LF halves (g, theta) and w~ of rows r-2 and r-1, by row parity
+  __shared__ T topr[2][3][NC][kWave];
   T Fg[NC], Ft[NC], Fx[NC];           // y-interface fluxes at (r-3)+1/2
   double smx = 0.0, smy = 0.0;
   unsigned flag = 0;
@@ -283,6 +288,10 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
         mT[c] = T(0.5) * (tt[c] + a_y * wT[c]);
         pG[c] = T(0.5) * (gb[c] - a_y * uB[c]);
         pT[c] = T(0.5) * (tb[c] - a_y * wB[c]);
+        const int pr = (r - 1) & 1;   // row r-1
+        topr[pr][0][c][lane] = mG[c];
+        topr[pr][1][c][lane] = mT[c];
+        topr[pr][2][c][lane] = wtn[c];
       }
     }
     if (r >= y0 + 1) {
@@ -292,13 +301,27 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         T Dg, Dt;
-        central_corr(g3[c], g2[c], g1[c], gc[c], t3[c], tc[c], hy, ihy, Dg, Dt);
-        Gn[c] = mGa[c] + pG[c] + Dg;
-        Tn[c] = mTa[c] + pT[c] + Dt;
-        Xn[c] = mixed_face(x3[c], x2[c], x1[c], xc[c]);
+        const int s3 = slot, s2 = slot == 2 ? 0 : slot + 1, s1 = slot == 0 ? 2 : slot - 1;
+        const T g3 = ring[s3][0][c][lane], g2 = ring[s2][0][c][lane], g1 = ring[s1][0][c][lane];
+        const T t3 = ring[s3][1][c][lane];
+        const T x3 = ring[s3][2][c][lane], x2 = ring[s2][2][c][lane], x1 = ring[s1][2][c][lane];
+        central_corr(g3, g2, g1, gc[c], t3, tc[c], hy, ihy, Dg, Dt);
+        const int pa = (r - 2) & 1;   // row r-2
+        Gn[c] = topr[pa][0][c][lane] + pG[c] + Dg;
+        Tn[c] = topr[pa][1][c][lane] + pT[c] + Dt;
+        Xn[c] = mixed_face(x3, x2, x1, xc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {   // row r takes the slot of row r-3
+        ring[slot][0][c][lane] = gc[c];
+        ring[slot][1][c][lane] = tc[c];
+        ring[slot][2][c][lane] = xc[c];
       }
       if (r >= y0 + 2) {
-        // output row o = r - 2: x-sweep of that row, then Step 4 and RK
+        // output row o = r - 2: x-sweep of that row, then Step 4 and RK.
+        // Keep the scheduler from interleaving it with the y-work above:
+        // both working sets live at once would spill.
+        __builtin_amdgcn_sched_barrier(0);
         const int o = r - 2;
         double RU[NC], RV[NC], RW[NC];
         T vt[NC];
@@ -317,16 +340,18 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
             Unew[c] = (T)rk<MODE>((double)Ua[c], ub, dt, Lu);
             A.Uo[idx] = Unew[c];
             A.Vo[idx] = (T)rk<MODE>((double)vt[c], vb, dt, Lv);
-            A.Wo[idx] = (T)rk<MODE>((double)wta[c], wb, dt, Lw);
+            const T wto = topr[(r - 2) & 1][2][c][lane];   // w~ of row o
+            A.Wo[idx] = (T)rk<MODE>((double)wto, wb, dt, Lw);
             if (MODE == kStage1 || MODE == kRhs) {
               A.Vt[idx] = vt[c];
-              A.Wt[idx] = wta[c];
+              A.Wt[idx] = wto;
             }
           }
           if (A.alpha_next) {
-            smx = fmax(smx, sy.template speed<0>(Unew));
-            smy = fmax(smy, sy.template speed<1>(Unew));
-            flag |= sy.admissible(Unew);
+            double sx_, sy_;
+            flag |= sy.speeds(Unew, sx_, sy_);
+            smx = fmax(smx, sx_);
+            smy = fmax(smy, sy_);
           }
         }
       }
@@ -336,14 +361,16 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
     // rotate the ring
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      g3[c] = g2[c]; g2[c] = g1[c]; g1[c] = gc[c];
-      t3[c] = t2[c]; t2[c] = t1[c]; t1[c] = tc[c];
-      x3[c] = x2[c]; x2[c] = x1[c]; x1[c] = xc[c];
+      if (r < y0 + 1) {
+        ring[slot][0][c][lane] = gc[c];
+        ring[slot][1][c][lane] = tc[c];
+        ring[slot][2][c][lane] = xc[c];
+      }
       Ua[c] = Ub[c]; Ub[c] = Uc[c];
       Va[c] = Vb[c]; Vb[c] = Vc[c];
       Wa[c] = Wb[c]; Wb[c] = Wc[c];
-      if (r >= y0) { mGa[c] = mG[c]; mTa[c] = mT[c]; wta[c] = wtn[c]; }
     }
+    slot = slot == 2 ? 0 : slot + 1;
   }
   if (A.alpha_next) {
     smx = wave_max(smx);
@@ -370,9 +397,10 @@ __global__ __launch_bounds__(256) void speed_partial_kernel(const T* U, int plan
     T u[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) u[c] = U[c * plane + i];
-    mx = fmax(mx, sy.template speed<0>(u));
-    if (DIM == 2) my = fmax(my, sy.template speed<1>(u));
-    flag |= sy.admissible(u);
+    double sx_, sy_;
+    flag |= sy.speeds(u, sx_, sy_);
+    mx = fmax(mx, sx_);
+    if (DIM == 2) my = fmax(my, sy_);
   }
   __shared__ double sx[4], sy_[4];
   __shared__ unsigned sf[4];
@@ -885,8 +913,37 @@ hweno_status dispatch(const hweno_problem* p, F&& f) {
   return p->precision == HWENO_F64 ? by_type(double{}) : by_type(float{});
 }
 
+// Strip height of the 2D marcher: enough row-blocks to fill whole rounds of
+// resident waves (CUs x waves per CU the kernel's registers and LDS allow),
+// so no round runs nearly empty; long strips also amortise the 4 warm-up
+// rows. At least 8 rows.
+template <class K>
+int strip_rows(K kernel, int mode, int nx, int ny) {
+  static std::atomic<int> per_cu_cache[4];   // per stage mode; 0 = not yet queried
+  int per_cu = per_cu_cache[mode].load(std::memory_order_relaxed);
+  if (per_cu <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
+        per_cu <= 0)
+      return 32;
+    per_cu_cache[mode].store(per_cu, std::memory_order_relaxed);
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 32;
+  const long cb = (nx + kXOut - 1) / kXOut;
+  const long slots = (long)cus * per_cu;
+  long rb = slots / cb;
+  if (rb < 1) rb = 1;
+  long rounds = 1;
+  int rows = (int)((ny + rb * rounds - 1) / (rb * rounds));
+  return rows < 8 ? 8 : rows;
+}
+
 template <class Sys, typename T, int DIM>
-hweno_status launch_stage(int mode, const StageArgs<T>& A, const Sys& sy, hipStream_t st) {
+hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipStream_t st) {
+  StageArgs<T> A = A0;
   if constexpr (DIM == 1) {
     dim3 grid((A.nx + kXOut - 1) / kXOut);
     switch (mode) {
@@ -896,12 +953,16 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A, const Sys& sy, hipStr
       default: stage1d_kernel<Sys, T, kStage3><<<grid, kWave, 0, st>>>(A, sy); break;
     }
   } else {
-    dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
+    auto go = [&](auto kernel) {
+      A.rows = strip_rows(kernel, mode, A.nx, A.ny);
+      dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
+      kernel<<<grid, kWave, 0, st>>>(A, sy);
+    };
     switch (mode) {
-      case kRhs: stage2d_kernel<Sys, T, kRhs><<<grid, kWave, 0, st>>>(A, sy); break;
-      case kStage1: stage2d_kernel<Sys, T, kStage1><<<grid, kWave, 0, st>>>(A, sy); break;
-      case kStage2: stage2d_kernel<Sys, T, kStage2><<<grid, kWave, 0, st>>>(A, sy); break;
-      default: stage2d_kernel<Sys, T, kStage3><<<grid, kWave, 0, st>>>(A, sy); break;
+      case kRhs: go(stage2d_kernel<Sys, T, kRhs>); break;
+      case kStage1: go(stage2d_kernel<Sys, T, kStage1>); break;
+      case kStage2: go(stage2d_kernel<Sys, T, kStage2>); break;
+      default: go(stage2d_kernel<Sys, T, kStage3>); break;
     }
   }
   return check_launch();

@@ -7,6 +7,7 @@
 // and "ALL OK" at the end; exits non-zero on failure.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -219,7 +220,57 @@ static void check_euler(const char* tag) {
   }
 }
 
+// The kernel's rearranged combination equals the direct form of (interp),
+// its mirror image and (limiter) written with the candidates p0, p1, p2.
+static void check_point_direct_form() {
+  double worst = 0.0;
+  for (int trial = 0; trial < 200; ++trial) {
+    const double h = unif(0.01, 1.0), g0 = unif(0.3, 0.99);
+    const Scheme s = scheme(h, g0);
+    const double um = unif(-2, 2), u0 = unif(-2, 2), up = unif(-2, 2);
+    const double vm = unif(-5, 5), vp = unif(-5, 5);
+    double uR, uL, vt;
+    hweno_point<double>(um, u0, up, vm, vp, s, h, 1.0 / h, uR, uL, vt);
+    const double e1 = u0 - um, e2 = up - u0;
+    double b0;
+    {
+      const double a1 = -h / 4 * (vm + vp) + 0.75 * (up - um);
+      const double a2 = h / 4 * (vm - vp) + (um - 2 * u0 + up);
+      const double a3 = h / 4 * (vm + vp) + 0.25 * (um - up);
+      const double a4 = h / 4 * (vp - vm) - 0.5 * (um - 2 * u0 + up);
+      b0 = (a1 + a3 / 4) * (a1 + a3 / 4) + 13.0 / 3 * (a2 + 63.0 / 130 * a4) * (a2 + 63.0 / 130 * a4) +
+           781.0 / 20 * a3 * a3 + 1421461.0 / 2275 * a4 * a4;
+    }
+    const double b[3] = {b0, e1 * e1, e2 * e2};
+    const double tau = 0.25 * std::pow(std::fabs(b[0] - b[1]) + std::fabs(b[0] - b[2]), 2);
+    auto weights = [&](const double lin[3], double w[3]) {
+      double sum = 0;
+      for (int l = 0; l < 3; ++l) { w[l] = lin[l] * (1 + tau / (b[l] + s.eps)); sum += w[l]; }
+      for (int l = 0; l < 3; ++l) w[l] /= sum;
+    };
+    const double lg[3] = {s.gamma0, s.g1, s.g1}, ld[3] = {s.d0, s.d1, s.d1};
+    double wg[3], wd[3];
+    weights(lg, wg);
+    weights(ld, wd);
+    auto comb = [](const double w[3], const double lin[3], double a, double bb, double c) {
+      return w[0] * (a / lin[0] - lin[1] / lin[0] * bb - lin[2] / lin[0] * c) + w[1] * bb + w[2] * c;
+    };
+    const double p0 = -um / 8 + 9.0 / 16 * u0 + 9.0 / 16 * up - h * (3.0 / 64 * vm + 9.0 / 64 * vp);
+    const double q0 = -up / 8 + 9.0 / 16 * u0 + 9.0 / 16 * um + h * (3.0 / 64 * vp + 9.0 / 64 * vm);
+    const double rR = comb(wg, lg, p0, -um / 2 + 1.5 * u0, (u0 + up) / 2);
+    const double rL = comb(wg, lg, q0, (um + u0) / 2, 1.5 * u0 - up / 2);
+    const double rT = comb(wd, ld, 3 / (4 * h) * (up - um) - (vm + vp) / 4, (u0 - um) / h, (up - u0) / h);
+    const double sc = 1 + std::fabs(u0) + std::fabs(up) + std::fabs(um) + h * (std::fabs(vm) + std::fabs(vp));
+    worst = std::max({worst, std::fabs(uR - rR) / sc, std::fabs(uL - rL) / sc,
+                      std::fabs(vt - rT) * h / sc});
+  }
+  const bool ok = worst < 1e-13;
+  if (!ok) ++failures;
+  std::printf("%-44s max err %.2e %s\n", "hweno_point = direct (interp)/(limiter)", worst, ok ? "ok" : "FAIL");
+}
+
 int main() {
+  check_point_direct_form();
   // HWENO point: smooth, near-critical, a jump, rough
   check_hweno_point("hweno_point smooth", {1.0, 1.1, 1.21, 2.0, 2.4}, 0.1, 0.95);
   check_hweno_point("hweno_point near extremum", {1.0, 1.0005, 0.9995, 0.02, -0.03}, 0.01, 0.95);
