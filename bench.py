@@ -210,6 +210,8 @@ def main():
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle baseline')
     ap.add_argument('--no-fp32', action='store_true', help='skip the FP32 form')
     ap.add_argument('--no-adjoint', action='store_true', help='skip the adjoint/forward ratio')
+    ap.add_argument('--adjoint-only', action='store_true',
+                    help='time only the adjoint workload (for profiling)')
     ap.add_argument('--probe', choices=['copy'], help='run a calibration probe instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
                     help='precision of the headline run')
@@ -227,6 +229,9 @@ def main():
     if not torch.cuda.is_available():
         print('bench.py: no HIP device visible', file=sys.stderr)
         sys.exit(1)
+    if args.adjoint_only:
+        print(json.dumps({'adjoint_f64': time_adjoint(args.precision)}))
+        return
 
     main_run = time_forward(args.n, args.precision, args.steps, args.warmup)
     fp32 = None

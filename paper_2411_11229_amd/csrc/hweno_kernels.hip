@@ -504,8 +504,8 @@ __global__ void ws_init_kernel(StepScalars* sc) {
 }
 
 // ================================================================ adjoint
-// Vector-Jacobian product of one stage for one direction, on lines laid out
-// along memory rows (the y direction runs on transposed copies). Given the
+// Vector-Jacobian product of one stage for the x direction, on lines laid
+// out along memory rows (1D, or each row of a 2D field). Given the
 // state X = (u, a, o) -- a the derivative along the line, o the other one --
 // and cotangents a_B of B(X) = (u, a~, ...) and b of L(X), it writes
 //   G = (dB/dX)^T a_B + (dL_dir/dX)^T b
@@ -692,67 +692,280 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   }
 }
 
+// y-direction VJP by marching up strips of rows (2D; natural layout, no
+// transposes). Each lane owns one column and needs no neighbour lane. The
+// strip's output rows [o0, o1) are virtual rows in [-2, ny+2): ghost-row
+// results go to a side buffer folded later by ghost_fold_rows_kernel. At
+// iteration r (row r loaded): the interface cotangents of (r-1)+1/2, the
+// reverse of row r-1's HWENO and face values (contributions to rows r-2..r),
+// and the reverse of row r-2's pointwise fluxes; row r-2 is then complete and
+// is added to G (which holds the x-direction result).
+template <typename T>
+struct VjpYArgs {
+  const T* X[3];          // u, v, w
+  const T* lam[3][3];     // cotangent sets [set][u, v, w]
+  double ca[3], cb[3];
+  int cb_dt;
+  const double* dt;
+  const double* alpha;    // [2]; uses alpha[1]
+  T* G[3];                // in/out: u, v, w
+  T* ghost;               // [4][3][NC][nx]: rows -2, -1, ny, ny+1
+  const T* xghost;        // x-pass ghost columns [ny][4][3][NC], folded here
+  int nx, ny, rows, plane;
+  int bc_lo, bc_hi;
+  int x_periodic;
+  Scheme s;
+};
+
+template <class Sys, typename T>
+__global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
+  constexpr int NC = Sys::NC;
+  using Bar = typename BarOf<Sys, T>::type;
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * kWave + lane;
+  const bool colok = x < A.nx;
+  const int xc = colok ? x : A.nx - 1;
+  const int o0 = -2 + blockIdx.y * A.rows;
+  const int o1 = min(o0 + A.rows, A.ny + 2);
+  const double dtv = A.dt ? *A.dt : 0.0;
+  const T alpha = T(A.alpha[1]);
+  const Scheme& s = A.s;
+  const T h = T(s.dy), ih = T(s.idy);
+  T ck[3], dk[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ck[k] = T(A.ca[k]);
+    dk[k] = T(A.cb[k] * (((A.cb_dt >> k) & 1) ? dtv : 1.0));
+  }
+  // interface cotangents (G, theta, xi) of the 3 previous interfaces, slot k mod 3
+  __shared__ T lring[3][3][NC][kWave];
+  T Ua[NC], Ub[NC], Va[NC], Vb[NC], Wa[NC], Wb[NC];   // rows r-2, r-1
+  T bU1[NC], bV1[NC], bW1[NC], aW1[NC];              // cotangents of row r-1
+  T accUa[NC], accWa[NC], accUb[NC], accWb[NC];      // HWENO-reverse sums of rows r-2, r-1
+#pragma unroll
+  for (int c = 0; c < NC; ++c) { accUa[c] = T(0); accWa[c] = T(0); accUb[c] = T(0); accWb[c] = T(0); }
+  for (int r = o0 - 2; r < o1 + 2; ++r) {
+    const int gr = map_index(r, A.ny, A.bc_lo, A.bc_hi);
+    const bool inrow = r >= 0 && r < A.ny;
+    T Uc[NC], Vc[NC], Wc[NC], bUc[NC], bVc[NC], bWc[NC], aWc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int idx = c * A.plane + gr * A.nx + xc;
+      Uc[c] = A.X[0][idx];
+      Vc[c] = A.X[1][idx];
+      Wc[c] = A.X[2][idx];
+      bUc[c] = T(0); bVc[c] = T(0); bWc[c] = T(0); aWc[c] = T(0);
+      if (inrow) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T lu = A.lam[k][0] ? A.lam[k][0][idx] : T(0);
+          const T lv = A.lam[k][1] ? A.lam[k][1][idx] : T(0);
+          const T lw = A.lam[k][2] ? A.lam[k][2][idx] : T(0);
+          bUc[c] += dk[k] * lu;
+          bVc[c] += dk[k] * lv;
+          bWc[c] += dk[k] * lw;
+          aWc[c] += ck[k] * lw;
+        }
+      }
+    }
+    // interface (r-1)+1/2: L_j = -(F_{j+1/2} - F_{j-1/2}) / dy
+    T lG[NC], lT[NC], lX[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      lG[c] = (bUc[c] - bU1[c]) * ih;
+      lT[c] = (bWc[c] - bW1[c]) * ih;
+      lX[c] = (bVc[c] - bV1[c]) * ih;
+    }
+    const int s1 = ((r - 1) % 3 + 3) % 3;        // slot of interface r-1 (and r-4)
+    const int s2 = s1 == 0 ? 2 : s1 - 1;          // interface r-2
+    const int s3 = s2 == 0 ? 2 : s2 - 1;          // interface r-3
+    T accUc[NC], accWc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) { accUc[c] = T(0); accWc[c] = T(0); }
+    if (r >= o0) {
+      // reverse of row r-1's faces: top face -> interface (r-1)+1/2 (minus
+      // side), bottom face -> interface (r-2)+1/2 (plus side)
+      T uT[NC], uB[NC], wt_[NC], wT[NC], wB[NC];
+      hweno_cell<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, uT, uB, wt_);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) face_derivs(Ua[c], Ub[c], Uc[c], Wa[c], Wc[c], ih, wT[c], wB[c]);
+      T hG[NC], hT[NC], pG[NC], pT[NC], guT[NC], gwT[NC], guB[NC], gwB[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        hG[c] = T(0.5) * lG[c];
+        hT[c] = T(0.5) * lT[c];
+        pG[c] = T(0.5) * lring[s2][0][c][lane];
+        pT[c] = T(0.5) * lring[s2][1][c][lane];
+        guT[c] = alpha * hG[c];
+        gwT[c] = alpha * hT[c];
+        guB[c] = -alpha * pG[c];
+        gwB[c] = -alpha * pT[c];
+      }
+      {
+        const auto qt = sy.prim(uT);
+        Bar bt{};
+        flux_vjp<1>(sy, uT, qt, hG, bt, guT);
+        jac_vjp<1>(sy, uT, qt, wT, hT, bt, guT, gwT);
+        prim_vjp(sy, uT, qt, bt, guT);
+        const auto qb = sy.prim(uB);
+        Bar bb{};
+        flux_vjp<1>(sy, uB, qb, pG, bb, guB);
+        jac_vjp<1>(sy, uB, qb, wB, pT, bb, guB, gwB);
+        prim_vjp(sy, uB, qb, bb, guB);
+      }
+      T tm[NC], tc[NC], tWm[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        tm[c] = T(0); tc[c] = T(0); tWm[c] = T(0);
+        face_derivs_vjp(gwT[c], gwB[c], ih, tm[c], tc[c], accUc[c], tWm[c], accWc[c]);
+      }
+      hweno_cell_vjp<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, guT, guB, aW1, tm, tc, accUc, tWm,
+                        accWc);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        accUa[c] += tm[c];
+        accWa[c] += tWm[c];
+        accUb[c] += tc[c];
+      }
+    }
+    if (r >= o0 + 2) {
+      // reverse of row r-2's pointwise g, theta, xi (interfaces r-4..r-1)
+      const int o = r - 2;
+      T gg[NC], gt[NC], gx[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const T G1 = lG[c], G0 = lring[s2][0][c][lane], Gm1 = lring[s3][0][c][lane], Gm2 = lring[s1][0][c][lane];
+        const T T1 = lT[c], T0 = lring[s2][1][c][lane], Tm1 = lring[s3][1][c][lane], Tm2 = lring[s1][1][c][lane];
+        const T X1 = lX[c], X0 = lring[s2][2][c][lane], Xm1 = lring[s3][2][c][lane], Xm2 = lring[s1][2][c][lane];
+        gg[c] = T(97.0 / 1920.0) * ((G0 + Gm1) - (G1 + Gm2)) +
+                ih * (T(697.0 / 5184.0) * (T1 - Tm2) + T(61.0 / 192.0) * (Tm1 - T0));
+        gt[c] = T(19.0 / 960.0) * h * (Gm2 - G1) + T(37.0 / 864.0) * (T1 + Tm2);
+        gx[c] = (T(7.0) * (X0 + Xm1) - (X1 + Xm2)) * T(1.0 / 12.0);
+      }
+      T gU[NC], gV[NC], gW[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) { gU[c] = accUa[c]; gW[c] = accWa[c]; gV[c] = T(0); }
+      const auto q = sy.prim(Ua);
+      Bar bq{};
+      flux_vjp<1>(sy, Ua, q, gg, bq, gU);
+      jac_vjp<1>(sy, Ua, q, Wa, gt, bq, gU, gW);
+      jac_vjp<1>(sy, Ua, q, Va, gx, bq, gU, gV);
+      prim_vjp(sy, Ua, q, bq, gU);
+      if (colok) {
+        if (o >= 0 && o < A.ny) {
+          // x-pass ghost columns of this row: their images are the edge columns
+          int sa = -1, sb = -1;
+          if (A.x_periodic) {
+            sa = x == A.nx - 2 ? 0 : x == A.nx - 1 ? 1 : x == 0 ? 2 : x == 1 ? 3 : -1;
+          } else if (x == 0) {
+            sa = 0; sb = 1;
+          } else if (x == A.nx - 1) {
+            sa = 2; sb = 3;
+          }
+          const T* xg = A.xghost + (size_t)o * 4 * 3 * NC;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const int idx = c * A.plane + o * A.nx + x;
+            T gx[3] = {A.G[0][idx], A.G[1][idx], A.G[2][idx]};
+            if (sa >= 0) {
+#pragma unroll
+              for (int f = 0; f < 3; ++f) {
+                gx[f] += xg[sa * 3 * NC + f * NC + c];
+                if (sb >= 0) gx[f] += xg[sb * 3 * NC + f * NC + c];
+              }
+            }
+            A.G[0][idx] = gx[0] + gU[c];
+            A.G[1][idx] = gx[1] + gV[c];
+            A.G[2][idx] = gx[2] + gW[c];
+          }
+        } else {
+          const int slot = o < 0 ? o + 2 : o - A.ny + 2;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            T* gp = A.ghost + ((size_t)slot * 3 * NC) * A.nx + x;
+            gp[(0 * NC + c) * A.nx] = gU[c];
+            gp[(1 * NC + c) * A.nx] = gV[c];
+            gp[(2 * NC + c) * A.nx] = gW[c];
+          }
+        }
+      }
+    }
+    // interface (r-1)+1/2 replaces (r-4)+1/2; rotate rows
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      lring[s1][0][c][lane] = lG[c];
+      lring[s1][1][c][lane] = lT[c];
+      lring[s1][2][c][lane] = lX[c];
+      Ua[c] = Ub[c]; Ub[c] = Uc[c];
+      Va[c] = Vb[c]; Vb[c] = Vc[c];
+      Wa[c] = Wb[c]; Wb[c] = Wc[c];
+      bU1[c] = bUc[c]; bV1[c] = bVc[c]; bW1[c] = bWc[c]; aW1[c] = aWc[c];
+      accUa[c] = accUb[c]; accWa[c] = accWb[c];
+      accUb[c] = accUc[c]; accWb[c] = accWc[c];
+    }
+  }
+}
+
+// Folds the ghost-row contributions of vjp_y_kernel into the rows they were
+// copied from (one thread per column, field and component; fixed order).
+// Periodic rows map -2, -1, ny, ny+1 to four distinct rows; transmissive rows
+// map the pairs to rows 0 and ny-1 (both sides share one boundary type).
+template <typename T>
+__global__ __launch_bounds__(256) void ghost_fold_rows_kernel(T* __restrict__ G0, T* __restrict__ G1,
+                                                              T* __restrict__ G2,
+                                                              const T* __restrict__ ghost, int nx,
+                                                              int ny, int plane, int nc, int periodic) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nx * 3 * nc) return;
+  const int x = t % nx;
+  const int fc = t / nx;            // f * nc + c
+  const int f = fc / nc, c = fc % nc;
+  T* G = (f == 0 ? G0 : (f == 1 ? G1 : G2)) + (size_t)c * plane + x;
+  const size_t gs = (size_t)3 * nc * nx;
+  const T* gp = ghost + (size_t)fc * nx + x;
+  const T g0 = gp[0], g1 = gp[gs], g2 = gp[2 * gs], g3 = gp[3 * gs];
+  if (periodic) {
+    const size_t r0 = (size_t)(ny - 2) * nx, r1 = (size_t)(ny - 1) * nx, r3 = (size_t)nx;
+    const T a0 = G[r0], a1 = G[r1], a2 = G[0], a3 = G[r3];
+    G[r0] = a0 + g0;
+    G[r1] = a1 + g1;
+    G[0] = a2 + g2;
+    G[r3] = a3 + g3;
+  } else {
+    const size_t rl = (size_t)(ny - 1) * nx;
+    const T a0 = G[0], a1 = G[rl];
+    G[0] = (a0 + g0) + g1;
+    G[rl] = (a1 + g2) + g3;
+  }
+}
+
 // Adds the ghost-cell contributions to the cells they were copied from, in a
 // fixed order (one thread per line, field and component).
 template <typename T>
-__global__ __launch_bounds__(256) void ghost_fold_kernel(T* G0, T* G1, T* G2, const T* ghost,
-                                                         int n, int rows, int plane, int nc,
-                                                         int nf, int bc_lo, int bc_hi) {
+__global__ __launch_bounds__(256) void ghost_fold_kernel(T* __restrict__ G0, T* __restrict__ G1,
+                                                         T* __restrict__ G2,
+                                                         const T* __restrict__ ghost, int n, int rows,
+                                                         int plane, int nc, int nf, int periodic) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = rows * nf * nc;
   if (t >= total) return;
   const int c = t % nc;
   const int f = (t / nc) % nf;
   const int row = t / (nc * nf);
-  T* G = f == 0 ? G0 : (f == 1 ? G1 : G2);
-  for (int slot = 0; slot < 4; ++slot) {
-    const int v = slot < 2 ? slot - 2 : n + slot - 2;
-    const int m = map_index(v, n, bc_lo, bc_hi);
-    G[c * plane + row * n + m] += ghost[((size_t)row * 4 + slot) * 3 * nc + f * nc + c];
-  }
-}
-
-// dst[p][x][y] (+)= sum_k coef_k src_k[p][y][x] for nplanes planes of
-// ny x nx; 32 x 32 tiles through LDS, coalesced on both sides.
-template <typename T>
-struct TArgs {
-  const T* src[3];
-  double coef[3];
-  int coef_dt;            // bit k: coef_k multiplied by *dt
-  const double* dt;
-  T* dst;
-  int accumulate;
-  int nx, ny, plane;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void transpose_kernel(TArgs<T> A) {
-  __shared__ T tile[32][33];
-  const int p = blockIdx.z;
-  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
-  const double dtv = A.dt ? *A.dt : 1.0;
-  T c[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) c[k] = T(A.coef[k] * (((A.coef_dt >> k) & 1) ? dtv : 1.0));
-  for (int j = threadIdx.y; j < 32; j += 8) {
-    const int x = x0 + threadIdx.x, y = y0 + j;
-    T val = T(0);
-    if (x < A.nx && y < A.ny) {
-      const int idx = p * A.plane + y * A.nx + x;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        if (A.src[k]) val += c[k] * A.src[k][idx];
-    }
-    tile[j][threadIdx.x] = val;
-  }
-  __syncthreads();
-  for (int j = threadIdx.y; j < 32; j += 8) {
-    const int y = y0 + threadIdx.x, x = x0 + j;
-    if (x < A.nx && y < A.ny) {
-      const int idx = p * A.plane + x * A.ny + y;
-      const T val = tile[threadIdx.x][j];
-      A.dst[idx] = A.accumulate ? A.dst[idx] + val : val;
-    }
+  T* G = (f == 0 ? G0 : (f == 1 ? G1 : G2)) + (size_t)c * plane + (size_t)row * n;
+  const T* gp = ghost + (size_t)row * 4 * 3 * nc + f * nc + c;
+  const int gs = 3 * nc;
+  const T g0 = gp[0], g1 = gp[gs], g2 = gp[2 * gs], g3 = gp[3 * gs];
+  if (periodic) {
+    const T a0 = G[n - 2], a1 = G[n - 1], a2 = G[0], a3 = G[1];
+    G[n - 2] = a0 + g0;
+    G[n - 1] = a1 + g1;
+    G[0] = a2 + g2;
+    G[1] = a3 + g3;
+  } else {
+    const T a0 = G[0], a1 = G[n - 1];
+    G[0] = (a0 + g0) + g1;
+    G[n - 1] = (a1 + g2) + g3;
   }
 }
 
@@ -815,9 +1028,8 @@ Geometry geometry(const hweno_problem* p) {
 // Workspace: scalars | per-block partial maxima | states | adjoint scratch.
 // States are stored densely ([field][comp][ny][nx]); each region starts on a
 // 256-byte boundary. Regions: X^(1), X^(2), the RK base derivatives
-// (V~^n[, W~^n]), and for the adjoint: lambda^(2), lambda^(1), the transposed
-// state, the transposed cotangents (b, then a), the transposed y-pass
-// result, and the ghost-cell side buffer.
+// (V~^n[, W~^n]), and for the adjoint: lambda^(2), lambda^(1) and the
+// ghost-cell side buffer.
 struct WsLayout {
   StepScalars* sc;
   double* partial;
@@ -826,27 +1038,25 @@ struct WsLayout {
   char* base;
   char* lam2;
   char* lam1;
-  char* xt;
-  char* bt;
-  char* at;
-  char* gt;
-  char* ghost;
+  char* ghost;     // x-pass ghost columns [ny][4][3][NC]
+  char* ghost_y;   // y-pass ghost rows [4][3][NC][nx]
   size_t state_bytes;
 };
 
 size_t state_bytes(const Geometry& g) { return align_up((size_t)g.nf * g.nc * g.plane * g.esize, 256); }
 size_t base_bytes(const Geometry& g) { return align_up((size_t)(g.nf - 1) * g.nc * g.plane * g.esize, 256); }
-size_t comp_bytes(const Geometry& g) { return align_up((size_t)g.nc * g.plane * g.esize, 256); }
-size_t ghost_bytes(const hweno_problem* p, const Geometry& g) {
-  const size_t lines = (size_t)(p->nx > p->ny ? p->nx : p->ny);
-  return align_up(lines * 4 * 3 * g.nc * g.esize, 256);
+size_t ghost_x_bytes(const hweno_problem* p, const Geometry& g) {
+  return align_up((size_t)p->ny * 4 * 3 * g.nc * g.esize, 256);
 }
+size_t ghost_y_bytes(const hweno_problem* p, const Geometry& g) {
+  return p->dim == 2 ? align_up((size_t)p->nx * 4 * 3 * g.nc * g.esize, 256) : 0;
+}
+size_t ghost_bytes(const hweno_problem* p, const Geometry& g) { return ghost_x_bytes(p, g) + ghost_y_bytes(p, g); }
 size_t ws_total(const hweno_problem* p, const Geometry& g) {
-  return kScalarBytes + kPartialBytes + 4 * state_bytes(g) + base_bytes(g) +
-         (g.nf == 3 ? 3 * state_bytes(g) + comp_bytes(g) : 0) + ghost_bytes(p, g);
+  return kScalarBytes + kPartialBytes + 4 * state_bytes(g) + base_bytes(g) + ghost_bytes(p, g);
 }
 
-WsLayout ws_layout(void* ws, const Geometry& g) {
+WsLayout ws_layout(const hweno_problem* p, void* ws, const Geometry& g) {
   WsLayout w;
   char* b = (char*)ws;
   w.sc = (StepScalars*)b;
@@ -857,17 +1067,8 @@ WsLayout ws_layout(void* ws, const Geometry& g) {
   w.base = w.x2 + w.state_bytes;
   w.lam2 = w.base + base_bytes(g);
   w.lam1 = w.lam2 + w.state_bytes;
-  char* nxt = w.lam1 + w.state_bytes;
-  if (g.nf == 3) {
-    w.xt = nxt;
-    w.bt = w.xt + w.state_bytes;
-    w.gt = w.bt + w.state_bytes;
-    w.at = w.gt + w.state_bytes;
-    nxt = w.at + comp_bytes(g);
-  } else {
-    w.xt = w.bt = w.gt = w.at = nullptr;
-  }
-  w.ghost = nxt;
+  w.ghost = w.lam1 + w.state_bytes;
+  w.ghost_y = w.ghost + ghost_x_bytes(p, g);
   return w;
 }
 
@@ -941,6 +1142,42 @@ int strip_rows(K kernel, int mode, int nx, int ny) {
   return rows < 8 ? 8 : rows;
 }
 
+// Strip height of the y-direction VJP marcher: blocks of 64 columns march
+// up strips of R of the `rows` virtual rows. A strip costs about R + 2.5 row
+// units (two extra HWENO reverses and two load-only rows), and the resident
+// waves (CUs x blocks per CU) run the blocks in rounds of equal length, so
+// R minimises rounds(R) * (R + 2.5).
+template <class K>
+int vjp_strip_rows(K kernel, int nx, int rows) {
+  static std::atomic<int> per_cu_cache{0};
+  int per_cu = per_cu_cache.load(std::memory_order_relaxed);
+  if (per_cu <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
+        per_cu <= 0)
+      return 16;
+    per_cu_cache.store(per_cu, std::memory_order_relaxed);
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 16;
+  const long cb = (nx + kWave - 1) / kWave;
+  const long slots = (long)cus * per_cu;
+  int best = rows;
+  double best_cost = 1e300;
+  for (int r = 1; r <= rows; ++r) {
+    const long blocks = cb * ((rows + r - 1) / r);
+    const long rounds = (blocks + slots - 1) / slots;
+    const double cost = (double)rounds * (r + 2.5);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = r;
+    }
+  }
+  return best;
+}
+
 template <class Sys, typename T, int DIM>
 hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipStream_t st) {
   StageArgs<T> A = A0;
@@ -995,8 +1232,8 @@ hweno_status launch_speed_partial(const hweno_problem* p, const T* U, const Sys&
   return check_launch();
 }
 
-// One VJP of a stage: x-pass on the arrays as stored, and in 2D a y-pass on
-// transposed copies, whose result is transposed back and added.
+// One VJP of a stage: the x-pass writes out[], the 2D y-pass marches up
+// column strips and adds to it; each pass then folds its ghost cells.
 struct CotSet {
   const void* f[3];       // u, v, w of one cotangent state (w null in 1D)
   double ca, cb;
@@ -1038,90 +1275,44 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
     vjp_row_kernel<Sys, T, 0, DIM + 1><<<grid, kWave, 0, st>>>(A, sy);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    const int tot = ny * g.nf * NC;
-    ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
-                                                           nx, ny, plane, NC, g.nf, p->bc[0], p->bc[1]);
-    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    if constexpr (DIM == 1) {   // in 2D the y-pass folds these
+      const int tot = ny * g.nf * NC;
+      ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
+                                                             nx, ny, plane, NC, g.nf,
+                                                             p->bc[0] == HWENO_PERIODIC);
+      if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    }
   }
   if constexpr (DIM == 2) {
-    const size_t cp = (size_t)NC * plane;
-    T* xt = (T*)wl.xt;
-    T* bt = (T*)wl.bt;
-    T* at = (T*)wl.at;
-    T* gt = (T*)wl.gt;
-    auto transpose = [&](const T* s0, const T* s1, const T* s2, const double c[3], int cdt, T* dst,
-                         int accumulate, int sx, int sy_) -> bool {
-      TArgs<T> t;
-      std::memset(&t, 0, sizeof(t));
-      t.src[0] = s0; t.src[1] = s1; t.src[2] = s2;
-      for (int k = 0; k < 3; ++k) t.coef[k] = c[k];
-      t.coef_dt = cdt;
-      t.dt = dt;
-      t.dst = dst;
-      t.accumulate = accumulate;
-      t.nx = sx;
-      t.ny = sy_;
-      t.plane = plane;
-      dim3 grid((sx + 31) / 32, (sy_ + 31) / 32, NC);
-      transpose_kernel<T><<<grid, dim3(32, 8), 0, st>>>(t);
-      return check_launch() == HWENO_OK;
-    };
-    const double one[3] = {1.0, 0.0, 0.0};
-    // state, with roles (u, along = w, other = v)
-    if (!transpose(X[0], nullptr, nullptr, one, 0, xt, 0, nx, ny)) return HWENO_EDEVICE;
-    if (!transpose(X[2], nullptr, nullptr, one, 0, xt + cp, 0, nx, ny)) return HWENO_EDEVICE;
-    if (!transpose(X[1], nullptr, nullptr, one, 0, xt + 2 * cp, 0, nx, ny)) return HWENO_EDEVICE;
-    // b (u, w, v roles) and the w-part of a_B
-    double cb[3] = {0, 0, 0}, ca[3] = {0, 0, 0};
-    int cdt = 0;
-    const T* lu[3] = {nullptr, nullptr, nullptr};
-    const T* lv[3] = {nullptr, nullptr, nullptr};
-    const T* lw[3] = {nullptr, nullptr, nullptr};
-    for (int k = 0; k < nsets; ++k) {
-      lu[k] = (const T*)sets[k].f[0];
-      lv[k] = (const T*)sets[k].f[1];
-      lw[k] = (const T*)sets[k].f[2];
-      cb[k] = sets[k].cb;
-      ca[k] = sets[k].ca;
-      if (sets[k].cb_dt) cdt |= 1 << k;
-    }
-    if (!transpose(lu[0], lu[1], lu[2], cb, cdt, bt, 0, nx, ny)) return HWENO_EDEVICE;
-    if (!transpose(lw[0], lw[1], lw[2], cb, cdt, bt + cp, 0, nx, ny)) return HWENO_EDEVICE;
-    if (!transpose(lv[0], lv[1], lv[2], cb, cdt, bt + 2 * cp, 0, nx, ny)) return HWENO_EDEVICE;
-    if (!transpose(lw[0], lw[1], lw[2], ca, 0, at, 0, nx, ny)) return HWENO_EDEVICE;
-    // y-pass on the transposed lines (length ny, nx of them)
-    VjpArgs<T> A;
+    VjpYArgs<T> A;
     std::memset(&A, 0, sizeof(A));
-    A.X[0] = xt; A.X[1] = xt + cp; A.X[2] = xt + 2 * cp;
-    A.lam[0][0] = bt; A.lam[0][1] = bt + cp; A.lam[0][2] = bt + 2 * cp;
-    A.ca[0] = 0.0; A.cb[0] = 1.0;
-    A.lam[1][1] = at;
-    A.ca[1] = 1.0; A.cb[1] = 0.0;
+    for (int f = 0; f < 3; ++f) A.X[f] = X[f];
+    for (int k = 0; k < nsets; ++k) {
+      for (int f = 0; f < 3; ++f) A.lam[k][f] = (const T*)sets[k].f[f];
+      A.ca[k] = sets[k].ca;
+      A.cb[k] = sets[k].cb;
+      if (sets[k].cb_dt) A.cb_dt |= 1 << k;
+    }
     A.dt = dt;
     A.alpha = alpha;
-    A.dir = 1;
-    A.add_identity = 0;
-    A.G[0] = gt; A.G[1] = gt + cp; A.G[2] = gt + 2 * cp;
-    A.ghost = (T*)wl.ghost;
-    A.n = ny;
-    A.rows = nx;
+    for (int f = 0; f < 3; ++f) A.G[f] = out[f];
+    A.ghost = (T*)wl.ghost_y;
+    A.xghost = (const T*)wl.ghost;
+    A.nx = nx;
+    A.ny = ny;
     A.plane = plane;
     A.bc_lo = p->bc[2];
     A.bc_hi = p->bc[3];
-    A.h = sc.dy;
-    A.ih = sc.idy;
+    A.x_periodic = p->bc[0] == HWENO_PERIODIC;
     A.s = sc;
-    dim3 grid((ny + 4 + kXOut - 1) / kXOut, nx);
-    vjp_row_kernel<Sys, T, 1, 3><<<grid, kWave, 0, st>>>(A, sy);
+    A.rows = vjp_strip_rows(vjp_y_kernel<Sys, T>, nx, ny + 4);
+    dim3 grid((nx + kWave - 1) / kWave, (ny + 4 + A.rows - 1) / A.rows);
+    vjp_y_kernel<Sys, T><<<grid, kWave, 0, st>>>(A, sy);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     const int tot = nx * 3 * NC;
-    ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(gt, gt + cp, gt + 2 * cp, (const T*)wl.ghost,
-                                                           ny, nx, plane, NC, 3, p->bc[2], p->bc[3]);
+    ghost_fold_rows_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost_y,
+                                                               nx, ny, plane, NC, p->bc[2] == HWENO_PERIODIC);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    // back: u += gt_u^T, w += gt_along^T, v += gt_other^T
-    if (!transpose(gt, nullptr, nullptr, one, 0, out[0], 1, ny, nx)) return HWENO_EDEVICE;
-    if (!transpose(gt + cp, nullptr, nullptr, one, 0, out[2], 1, ny, nx)) return HWENO_EDEVICE;
-    if (!transpose(gt + 2 * cp, nullptr, nullptr, one, 0, out[1], 1, ny, nx)) return HWENO_EDEVICE;
   }
   return HWENO_OK;
 }
@@ -1166,7 +1357,7 @@ hweno_status hweno_max_wavespeed(const hweno_problem* p, const void* u, double* 
   if (st != HWENO_OK) return st;
   if (!u || !alpha || !ws) return HWENO_EINVAL;
   const Geometry g = geometry(p);
-  WsLayout w = ws_layout(ws, g);
+  WsLayout w = ws_layout(p, ws, g);
   return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
     using T = decltype(tag);
     using Sys = decltype(sy);
@@ -1226,7 +1417,7 @@ hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void*
   if (dt_rule == HWENO_DT_FIXED ? !(dt_fixed > 0.0) : !(cfl > 0.0)) return HWENO_EINVAL;
   if (std::isnan(t_end)) return HWENO_EINVAL;
   const Geometry g = geometry(p);
-  WsLayout wl = ws_layout(ws, g);
+  WsLayout wl = ws_layout(p, ws, g);
   return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
     using T = decltype(tag);
     using Sys = decltype(sy);
@@ -1305,7 +1496,7 @@ hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w
   if (p->dim == 2 && !w) return HWENO_EINVAL;
   if (p->dim == 1 && w) return HWENO_EINVAL;
   const Geometry g = geometry(p);
-  WsLayout wl = ws_layout(ws, g);
+  WsLayout wl = ws_layout(p, ws, g);
   return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
     using T = decltype(tag);
     using Sys = decltype(sy);
@@ -1355,7 +1546,7 @@ hweno_status hweno_adjoint_step(const hweno_problem* p, const void* u_n, const v
     for (auto i : ins)
       if (o && i && o == i) return HWENO_EINVAL;
   const Geometry g = geometry(p);
-  WsLayout wl = ws_layout(ws, g);
+  WsLayout wl = ws_layout(p, ws, g);
   return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
     using T = decltype(tag);
     using Sys = decltype(sy);

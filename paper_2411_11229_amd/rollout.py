@@ -48,21 +48,34 @@ class HwenoRollout(torch.autograd.Function):
                                                                         device=s.device)
                for g in grads[:nf]]
         out = [s.new_state() for _ in range(nf)]
-        per_stage = 2 * nf * s.prob.ncomp * s.prob.nx * s.prob.ny
+        plane = s.prob.ncomp * s.prob.nx * s.prob.ny
+        per_stage = 2 * nf * plane
         stage_buf = (torch.empty(every, per_stage, dtype=s.prob.dtype, device=s.device)
                      if ctx.store_stages else None)
+        # step-start states of one segment, each (U, V[, W]) contiguous, so a
+        # step costs one device copy
+        starts = torch.empty(every + 1, nf * plane, dtype=s.prob.dtype, device=s.device)
+
+        def fields(k):
+            return [starts[k, f * plane:(f + 1) * plane].view(s.prob.shape) for f in range(nf)]
+
         for seg, start in reversed(list(enumerate(range(0, ctx.steps, every)))):
             end = min(start + every, ctx.steps)
-            U, V, W = (x.clone() if x is not None else None for x in ctx.ckpts[seg])
-            starts = []
+            for dst, src in zip(fields(0), ctx.ckpts[seg]):
+                dst.copy_(src)
             for k in range(start, end):
-                starts.append((U.clone(), V.clone(), W.clone() if two else None))
-                st = stage_buf[k - start] if stage_buf is not None else None
-                s.step_frozen(U, V, W, ctx.dts[k:k + 1], ctx.recs[k], stages=st)
+                j = k - start
+                starts[j + 1].copy_(starts[j])
+                X = fields(j + 1)
+                st = stage_buf[j] if stage_buf is not None else None
+                s.step_frozen(X[0], X[1], X[2] if two else None, ctx.dts[k:k + 1], ctx.recs[k],
+                              stages=st)
             for k in reversed(range(start, end)):
-                Xk = starts[k - start]
-                st = stage_buf[k - start] if stage_buf is not None else None
-                s.adjoint_step(Xk[0], Xk[1], Xk[2], ctx.dts[k:k + 1], ctx.recs[k], lam, out, stages=st)
+                j = k - start
+                X = fields(j)
+                st = stage_buf[j] if stage_buf is not None else None
+                s.adjoint_step(X[0], X[1], X[2] if two else None, ctx.dts[k:k + 1], ctx.recs[k], lam,
+                               out, stages=st)
                 lam, out = out, lam
         gU, gV = lam[0], lam[1]
         gW = lam[2] if two else None

@@ -49,8 +49,10 @@ def _ws_bytes(lib, p):
 def test_workspace_size_valid_problem(lib):
     st, n = _ws_bytes(lib, _prob())
     assert st == 0
-    # 5 states of 12 planes plus 4 base planes, float64, plus scalars
-    assert n >= (5 * 12 + 4) * 64 * 48 * 8
+    # X^(1), X^(2), lambda^(2), lambda^(1): 4 states of 3 fields x 4
+    # components; the RK base derivatives: 2 x 4 planes; float64, plus the
+    # scalars, partial maxima and ghost buffer
+    assert n >= (4 * 12 + 8) * 64 * 48 * 8
     st32, n32 = _ws_bytes(lib, _prob(precision='f32'))
     assert st32 == 0 and n32 < n
 
