@@ -34,14 +34,14 @@ struct Scheme {
 
 // ---------------------------------------------------------------- lane shifts
 // Values of the neighbouring lane along x (lanes are consecutive cells).
-// DPP wave_shr:1 / wave_shl:1 row moves: lane i receives lane i-1 / i+1 (a
-// lane without a source keeps its own value). They execute as VALU moves,
-// with no LDS round trip.
+// DPP wave_shr:1 / wave_shl:1 row moves: lane i receives lane i-1 / i+1; the
+// lane without a source (0, resp. 63) receives 0, which only halo lanes see.
+// One VALU move per 32-bit word, with no LDS round trip.
 __device__ __forceinline__ int dpp_prev_i32(int x) {
-  return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(x, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int dpp_next_i32(int x) {
-  return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(x, 0x130, 0xf, 0xf, true);
 }
 template <typename T> __device__ __forceinline__ T from_prev(T x);
 template <typename T> __device__ __forceinline__ T from_next(T x);
@@ -118,7 +118,9 @@ HWENO_HD float rsqrt_nr(float x) {
 //
 // Arithmetic: with r_l = tau/(beta_l + eps), o_l = 1 + r_l, the normalised
 // weights are w_l = lin_l o_l / S, S = gamma0 o0 + g1 (o1 + o2) (gamma1 =
-// gamma2 = g1, the paper's choice). Written through the one-sided
+// gamma2 = g1, the paper's choice). The o_l are used multiplied by the
+// positive common factor (beta0+eps)(beta1+eps)(beta2+eps), which the
+// normalisations cancel, so no division is needed for the ratios. Written through the one-sided
 // differences e1 = u_i - u_{i-1}, e2 = u_{i+1} - u_i, the candidates are
 // p1 = u_i + e1/2, p2 = u_i + e2/2 and p0 = u_i + e1/8 + 9e2/16 -
 // dx(3v_{i-1} + 9v_{i+1})/64; the u_i terms of (interp) add up to u_i S, so
@@ -127,48 +129,58 @@ HWENO_HD float rsqrt_nr(float x) {
 //   v~_i        = [o0 ((3/4 - d1)(e1 + e2)/dx - (v_{i-1} + v_{i+1})/4) + d1 X/dx] / S_d,
 // with X = o1 e1 + o2 e2, B_R = k1 e1 + k2 e2 - dx(3v_{i-1} + 9v_{i+1})/64,
 // B_L = k2 e1 + k1 e2 - dx(9v_{i-1} + 3v_{i+1})/64, k1 = 1/8 - g1/2,
-// k2 = 9/16 - g1/2 and S_d = d0 o0 + d1 (o1 + o2). The three ratios share one
-// division, both normalisations another.
+// k2 = 9/16 - g1/2 and S_d = d0 o0 + d1 (o1 + o2). Both normalisations
+// share one division. Range: the scaled o_l grow like beta^4, so the product
+// of the normalisations stays finite for jumps below about 1e17 in the
+// variable interpolated.
 template <typename T>
 HWENO_HD void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
                                             double h, double ih, T& uR, T& uL, T& vt) {
   const double dc = (double)u0;
   const double e1 = dc - (double)um, e2 = (double)up - dc;
   const double vmd = (double)vm, vpd = (double)vp;
-  const double hvm = h * vmd, hvp = h * vpd;
-  // (GHYZ) closed form: cdf = u_{i+1} - u_{i-1}, sdf = u_{i-1} - 2u_i + u_{i+1}
+  // (GHYZ) closed form: cdf = u_{i+1} - u_{i-1}, sdf = u_{i-1} - 2u_i + u_{i+1},
+  // sv = dx (v_{i-1} + v_{i+1})/4, dv = dx (v_{i-1} - v_{i+1})/4
   const double cdf = e1 + e2, sdf = e2 - e1;
-  const double sv = 0.25 * (hvm + hvp), dv = 0.25 * (hvm - hvp);
-  const double a3 = sv - 0.25 * cdf;
-  const double a4 = -0.5 * sdf - dv;
-  const double t1 = 0.6875 * cdf - 0.75 * sv;                     // a1 + a3/4
-  const double t2 = (197.0 / 260.0) * sdf + (67.0 / 130.0) * dv;  // a2 + 63/130 a4
-  const double b0 = t1 * t1 + (13.0 / 3.0) * t2 * t2 + (781.0 / 20.0) * a3 * a3 +
-                    (1421461.0 / 2275.0) * a4 * a4;
+  const double qh = 0.25 * h;
+  const double sv = qh * (vmd + vpd), dv = qh * (vmd - vpd);
+  // beta0 = t1^2 + 13/3 t2^2 + 781/20 a3^2 + 1421461/2275 a4^2 with
+  // t1 = a1 + a3/4, t2 = a2 + 63/130 a4, a3 = sv - cdf/4, a4 = -sdf/2 - dv;
+  // the weights' square roots are folded into the combinations
+  constexpr double r13 = 2.0816659994661326;    // sqrt(13/3)
+  constexpr double r781 = 6.248999919987197;    // sqrt(781/20)
+  constexpr double r1421 = 24.99636017459386;   // sqrt(1421461/2275)
+  const double t1 = 0.6875 * cdf - 0.75 * sv;
+  const double t2 = (r13 * 197.0 / 260.0) * sdf + (r13 * 67.0 / 130.0) * dv;
+  const double a3 = r781 * sv - (0.25 * r781) * cdf;
+  const double a4 = (-0.5 * r1421) * sdf - r1421 * dv;
+  const double b0 = t1 * t1 + t2 * t2 + a3 * a3 + a4 * a4;
   const double b1 = e1 * e1, b2 = e2 * e2;
   // (nonlinear)
   const double ts = fabs(b0 - b1) + fabs(b0 - b2);
   const double tau = 0.25 * ts * ts;
   const double q0 = b0 + s.eps, q1 = b1 + s.eps, q2 = b2 + s.eps;
-  const double q12 = q1 * q2;
-  const double ti = tau * rcp_nr(q0 * q12);
-  const double o0 = 1.0 + ti * q12;           // 1 + tau/(beta0+eps)
-  const double o1 = 1.0 + ti * (q0 * q2);     // 1 + tau/(beta1+eps)
-  const double o2 = 1.0 + ti * (q0 * q1);     // 1 + tau/(beta2+eps)
+  // o_l scaled by P = q0 q1 q2 > 0 (every result below is homogeneous of
+  // degree 0 in the o_l): P o_l = P + tau P/q_l
+  const double o0 = (q1 * q2) * (q0 + tau);
+  const double o1 = (q0 * q2) * (q1 + tau);
+  const double o2 = (q0 * q1) * (q2 + tau);
   const double o12 = o1 + o2;
   const double Sg = s.gamma0 * o0 + s.g1 * o12;
   const double Sd = s.d0 * o0 + s.d1 * o12;
   const double inv = rcp_nr(Sg * Sd);
   const double iSg = Sd * inv, iSd = Sg * inv;
-  // (Pxi), its mirror image and (limiter-p), combined as above
+  // (Pxi), its mirror image and (limiter-p), combined as above; with
+  // K = (k1 + k2)/2 and k2 - k1 = 7/16: B_R = base + m, B_L = base - m
   const double X = o1 * e1 + o2 * e2;
   const double gX = 0.5 * s.g1 * X;
-  const double k1 = 0.125 - 0.5 * s.g1, k2 = 0.5625 - 0.5 * s.g1;
-  const double BR = k1 * e1 + k2 * e2 - (0.046875 * hvm + 0.140625 * hvp);
-  const double BL = k2 * e1 + k1 * e2 - (0.140625 * hvm + 0.046875 * hvp);
-  uR = (T)(dc + (o0 * BR + gX) * iSg);
-  uL = (T)(dc - (o0 * BL + gX) * iSg);
-  const double AT = (0.75 - s.d1) * ih * cdf - 0.25 * (vmd + vpd);
+  const double K = 0.34375 - 0.5 * s.g1;
+  const double base = K * cdf - 0.375 * sv;
+  const double m = 0.21875 * sdf + 0.1875 * dv;
+  const double P1 = o0 * base + gX, P2 = o0 * m;
+  uR = (T)(dc + (P1 + P2) * iSg);
+  uL = (T)(dc - (P1 - P2) * iSg);
+  const double AT = (0.75 - s.d1) * ih * cdf - ih * sv;
   vt = (T)((o0 * AT + s.d1 * ih * X) * iSd);
 }
 
