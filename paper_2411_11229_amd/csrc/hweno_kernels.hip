@@ -517,9 +517,10 @@ __global__ void ws_init_kernel(StepScalars* sc) {
 template <typename T>
 struct VjpArgs {
   const T* X[3];          // u, along-derivative, other derivative (null in 1D)
-  const T* lam[3][3];     // cotangent sets [set][u, along, other]; null = zero
-  double ca[3], cb[3];    // a_B = sum ca_k lam_k, b = sum cb_k lam_k
-  int cb_dt;              // bit k set: cb_k is multiplied by *dt
+  const T* b[3];          // b = cb dt lam_b: the one cotangent state L sees
+  const T* a[3][2];       // a_B = sum_k ca_k lam_k (u and along fields)
+  double ca[3];
+  double cb;              // multiplied by *dt
   const double* dt;
   const double* alpha;    // [2]; this pass uses alpha[dir]
   int dir;
@@ -532,7 +533,7 @@ struct VjpArgs {
   Scheme s;
 };
 
-template <class Sys, typename T, int D, int NF>
+template <class Sys, typename T, int D, int NF, int NA>
 __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   using Bar = typename BarOf<Sys, T>::type;
@@ -560,21 +561,17 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) { aU[c] = T(0); aA[c] = T(0); bU[c] = T(0); bA[c] = T(0); bO[c] = T(0); }
   if (interior) {
+    const T cbt = T(A.cb * dtv);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const T ck = T(A.ca[k]);
-      const T dk = T(A.cb[k] * (((A.cb_dt >> k) & 1) ? dtv : 1.0));
+    for (int c = 0; c < NC; ++c) {
+      const int idx = c * A.plane + base + v;
+      bU[c] = cbt * A.b[0][idx];
+      bA[c] = cbt * A.b[1][idx];
+      if (NF == 3) bO[c] = cbt * A.b[2][idx];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int idx = c * A.plane + base + v;
-        const T lu = A.lam[k][0] ? A.lam[k][0][idx] : T(0);
-        const T la = A.lam[k][1] ? A.lam[k][1][idx] : T(0);
-        const T lo = (NF == 3 && A.lam[k][2]) ? A.lam[k][2][idx] : T(0);
-        aU[c] += ck * lu;
-        aA[c] += ck * la;
-        bU[c] += dk * lu;
-        bA[c] += dk * la;
-        bO[c] += dk * lo;
+      for (int k = 0; k < NA; ++k) {
+        aU[c] += T(A.ca[k]) * A.a[k][0][idx];
+        aA[c] += T(A.ca[k]) * A.a[k][1][idx];
       }
     }
   }
@@ -703,9 +700,11 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
 template <typename T>
 struct VjpYArgs {
   const T* X[3];          // u, v, w
-  const T* lam[3][3];     // cotangent sets [set][u, v, w]
-  double ca[3], cb[3];
-  int cb_dt;
+  const T* b[3];          // b = cb dt lam_b (u, v, w)
+  const T* aw[3];         // w fields of the a sets: a_w = sum_k ca_k lam_k,w
+  double ca[3];
+  double cb;              // multiplied by *dt
+  int na;                 // number of a sets (1 or 3)
   const double* dt;
   const double* alpha;    // [2]; uses alpha[1]
   T* G[3];                // in/out: u, v, w
@@ -731,12 +730,7 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
   const T alpha = T(A.alpha[1]);
   const Scheme& s = A.s;
   const T h = T(s.dy), ih = T(s.idy);
-  T ck[3], dk[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    ck[k] = T(A.ca[k]);
-    dk[k] = T(A.cb[k] * (((A.cb_dt >> k) & 1) ? dtv : 1.0));
-  }
+  const T cbt = T(A.cb * dtv);
   // interface cotangents (G, theta, xi) of the 3 previous interfaces, slot k mod 3
   __shared__ T lring[3][3][NC][kWave];
   T Ua[NC], Ub[NC], Va[NC], Vb[NC], Wa[NC], Wb[NC];   // rows r-2, r-1
@@ -756,16 +750,10 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
       Wc[c] = A.X[2][idx];
       bUc[c] = T(0); bVc[c] = T(0); bWc[c] = T(0); aWc[c] = T(0);
       if (inrow) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const T lu = A.lam[k][0] ? A.lam[k][0][idx] : T(0);
-          const T lv = A.lam[k][1] ? A.lam[k][1][idx] : T(0);
-          const T lw = A.lam[k][2] ? A.lam[k][2][idx] : T(0);
-          bUc[c] += dk[k] * lu;
-          bVc[c] += dk[k] * lv;
-          bWc[c] += dk[k] * lw;
-          aWc[c] += ck[k] * lw;
-        }
+        bUc[c] = cbt * A.b[0][idx];
+        bVc[c] = cbt * A.b[1][idx];
+        bWc[c] = cbt * A.b[2][idx];
+        for (int k = 0; k < A.na; ++k) aWc[c] += T(A.ca[k]) * A.aw[k][idx];
       }
     }
     // interface (r-1)+1/2: L_j = -(F_{j+1/2} - F_{j-1/2}) / dy
@@ -1147,9 +1135,9 @@ int strip_rows(K kernel, int mode, int nx, int ny) {
 // units (two extra HWENO reverses and two load-only rows), and the resident
 // waves (CUs x blocks per CU) run the blocks in rounds of equal length, so
 // R minimises rounds(R) * (R + 2.5).
-template <class K>
+template <int TAG, class K>
 int vjp_strip_rows(K kernel, int nx, int rows) {
-  static std::atomic<int> per_cu_cache{0};
+  static std::atomic<int> per_cu_cache{0};   // one per kernel instance (TAG)
   int per_cu = per_cu_cache.load(std::memory_order_relaxed);
   if (per_cu <= 0) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
@@ -1234,15 +1222,17 @@ hweno_status launch_speed_partial(const hweno_problem* p, const T* U, const Sys&
 
 // One VJP of a stage: the x-pass writes out[], the 2D y-pass marches up
 // column strips and adds to it; each pass then folds its ghost cells.
-struct CotSet {
-  const void* f[3];       // u, v, w of one cotangent state (w null in 1D)
-  double ca, cb;
-  bool cb_dt;
+struct Cot {
+  const void* b[3];       // the flux cotangent state (u, v, w; w null in 1D), scaled by cb dt
+  double cb;
+  const void* a[3][3];    // the a sets (u, v, w each)
+  double ca[3];
+  int na;                 // 1 or 3
 };
 
 template <class Sys, typename T, int DIM>
 hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g,
-                        const WsLayout& wl, const T* X[3], const CotSet* sets, int nsets,
+                        const WsLayout& wl, const T* X[3], const Cot& cot,
                         const double* alpha, const double* dt, T* out[3], hipStream_t st) {
   constexpr int NC = Sys::NC;
   const Scheme sc = make_scheme(p);
@@ -1251,13 +1241,16 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   {
     VjpArgs<T> A;
     std::memset(&A, 0, sizeof(A));
-    for (int f = 0; f < 3; ++f) A.X[f] = X[f];
-    for (int k = 0; k < nsets; ++k) {
-      for (int f = 0; f < 3; ++f) A.lam[k][f] = (const T*)sets[k].f[f];
-      A.ca[k] = sets[k].ca;
-      A.cb[k] = sets[k].cb;
-      if (sets[k].cb_dt) A.cb_dt |= 1 << k;
+    for (int f = 0; f < 3; ++f) {
+      A.X[f] = X[f];
+      A.b[f] = (const T*)cot.b[f];
     }
+    for (int k = 0; k < cot.na; ++k) {
+      A.a[k][0] = (const T*)cot.a[k][0];
+      A.a[k][1] = (const T*)cot.a[k][1];
+      A.ca[k] = cot.ca[k];
+    }
+    A.cb = cot.cb;
     A.dt = dt;
     A.alpha = alpha;
     A.dir = 0;
@@ -1273,7 +1266,10 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.ih = sc.idx;
     A.s = sc;
     dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
-    vjp_row_kernel<Sys, T, 0, DIM + 1><<<grid, kWave, 0, st>>>(A, sy);
+    if (cot.na == 1)
+      vjp_row_kernel<Sys, T, 0, DIM + 1, 1><<<grid, kWave, 0, st>>>(A, sy);
+    else
+      vjp_row_kernel<Sys, T, 0, DIM + 1, 3><<<grid, kWave, 0, st>>>(A, sy);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     if constexpr (DIM == 1) {   // in 2D the y-pass folds these
       const int tot = ny * g.nf * NC;
@@ -1286,13 +1282,16 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   if constexpr (DIM == 2) {
     VjpYArgs<T> A;
     std::memset(&A, 0, sizeof(A));
-    for (int f = 0; f < 3; ++f) A.X[f] = X[f];
-    for (int k = 0; k < nsets; ++k) {
-      for (int f = 0; f < 3; ++f) A.lam[k][f] = (const T*)sets[k].f[f];
-      A.ca[k] = sets[k].ca;
-      A.cb[k] = sets[k].cb;
-      if (sets[k].cb_dt) A.cb_dt |= 1 << k;
+    for (int f = 0; f < 3; ++f) {
+      A.X[f] = X[f];
+      A.b[f] = (const T*)cot.b[f];
     }
+    for (int k = 0; k < cot.na; ++k) {
+      A.aw[k] = (const T*)cot.a[k][2];
+      A.ca[k] = cot.ca[k];
+    }
+    A.na = cot.na;
+    A.cb = cot.cb;
     A.dt = dt;
     A.alpha = alpha;
     for (int f = 0; f < 3; ++f) A.G[f] = out[f];
@@ -1305,9 +1304,12 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.bc_hi = p->bc[3];
     A.x_periodic = p->bc[0] == HWENO_PERIODIC;
     A.s = sc;
-    A.rows = vjp_strip_rows(vjp_y_kernel<Sys, T>, nx, ny + 4);
-    dim3 grid((nx + kWave - 1) / kWave, (ny + 4 + A.rows - 1) / A.rows);
-    vjp_y_kernel<Sys, T><<<grid, kWave, 0, st>>>(A, sy);
+    auto go = [&](auto kernel, int rows) {
+      A.rows = rows;
+      dim3 grid((nx + kWave - 1) / kWave, (ny + 4 + A.rows - 1) / A.rows);
+      kernel<<<grid, kWave, 0, st>>>(A, sy);
+    };
+    go(vjp_y_kernel<Sys, T>, vjp_strip_rows<0>(vjp_y_kernel<Sys, T>, nx, ny + 4));
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     const int tot = nx * 3 * NC;
     ghost_fold_rows_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost_y,
@@ -1582,18 +1584,35 @@ hweno_status hweno_adjoint_step(const hweno_problem* p, const void* u_n, const v
     const T* X1[3] = {F(x1, 0), F(x1, 1), DIM == 2 ? F(x1, 2) : nullptr};
     const T* X0[3] = {(const T*)u_n, (const T*)v_n, (const T*)w_n};
     // lambda^(2) = vjp(X^(2); 2/3 lambda, 2/3 dt lambda)
-    CotSet s3 = {{lam_u_in, lam_v_in, lam_w_in}, 2.0 / 3.0, 2.0 / 3.0, true};
-    if ((s2 = launch_vjp<Sys, T, DIM>(p, sy, g, wl, X2, &s3, 1, alpha_rec + 4, dt, l2, stream)) != HWENO_OK)
+    const void* lin[3] = {lam_u_in, lam_v_in, lam_w_in};
+    Cot c3{};
+    for (int f = 0; f < 3; ++f) c3.b[f] = c3.a[0][f] = lin[f];
+    c3.cb = 2.0 / 3.0;
+    c3.ca[0] = 2.0 / 3.0;
+    c3.na = 1;
+    if ((s2 = launch_vjp<Sys, T, DIM>(p, sy, g, wl, X2, c3, alpha_rec + 4, dt, l2, stream)) != HWENO_OK)
       return s2;
     // lambda^(1) = vjp(X^(1); 1/4 lambda^(2), 1/4 dt lambda^(2))
-    CotSet s22 = {{l2[0], l2[1], l2[2]}, 0.25, 0.25, true};
-    if ((s2 = launch_vjp<Sys, T, DIM>(p, sy, g, wl, X1, &s22, 1, alpha_rec + 2, dt, l1, stream)) != HWENO_OK)
+    Cot c2{};
+    for (int f = 0; f < 3; ++f) c2.b[f] = c2.a[0][f] = l2[f];
+    c2.cb = 0.25;
+    c2.ca[0] = 0.25;
+    c2.na = 1;
+    if ((s2 = launch_vjp<Sys, T, DIM>(p, sy, g, wl, X1, c2, alpha_rec + 2, dt, l1, stream)) != HWENO_OK)
       return s2;
     // lambda^n = vjp(X^n; lambda^(1) + 3/4 lambda^(2) + 1/3 lambda, dt lambda^(1))
-    CotSet s1[3] = {{{l1[0], l1[1], l1[2]}, 1.0, 1.0, true},
-                    {{l2[0], l2[1], l2[2]}, 0.75, 0.0, false},
-                    {{lam_u_in, lam_v_in, lam_w_in}, 1.0 / 3.0, 0.0, false}};
-    return launch_vjp<Sys, T, DIM>(p, sy, g, wl, X0, s1, 3, alpha_rec, dt, lo, stream);
+    Cot c1{};
+    for (int f = 0; f < 3; ++f) {
+      c1.b[f] = c1.a[0][f] = l1[f];
+      c1.a[1][f] = l2[f];
+      c1.a[2][f] = lin[f];
+    }
+    c1.cb = 1.0;
+    c1.ca[0] = 1.0;
+    c1.ca[1] = 0.75;
+    c1.ca[2] = 1.0 / 3.0;
+    c1.na = 3;
+    return launch_vjp<Sys, T, DIM>(p, sy, g, wl, X0, c1, alpha_rec, dt, lo, stream);
   });
 }
 

@@ -9,7 +9,9 @@ checkpoint of the state every ``checkpoint_every`` steps; the backward re-runs
 one segment at a time from its checkpoint with the recorded dt and alphas
 (``hweno_step_frozen``), keeping that segment's step-start states and, by
 default, its stage states X^(1), X^(2), so the adjoint of a step needs no
-forward recomputation.
+forward recomputation. The last segment, which the backward needs first, is
+kept by the forward itself (step-start and stage states, written by the
+steps it takes anyway), so only the earlier segments are recomputed.
 """
 import torch
 
@@ -30,14 +32,29 @@ class HwenoRollout(torch.autograd.Function):
         dts = torch.zeros(steps, dtype=torch.float64, device=dev)
         recs = torch.zeros(steps, 6, dtype=torch.float64, device=dev)
         ckpts = []
+        nf = 3 if two else 2
+        plane = solver.prob.ncomp * solver.prob.nx * solver.prob.ny
+        last = ((steps - 1) // checkpoint_every) * checkpoint_every if steps > 0 else 0
+        n_last = steps - last
+        # the last segment's step-start states and (optionally) stage states
+        seg_states = torch.empty(checkpoint_every + 1, nf * plane, dtype=solver.prob.dtype, device=dev)
+        seg_stages = (torch.empty(checkpoint_every, 2 * nf * plane, dtype=solver.prob.dtype,
+                                  device=dev) if store_stages else None)
         for k in range(steps):
             if k % checkpoint_every == 0:
                 ckpts.append((U.clone(), V.clone(), W.clone() if two else None))
+            st = None
+            if k >= last:
+                j = k - last
+                for f, x in enumerate((U, V, W)[:nf]):
+                    seg_states[j, f * plane:(f + 1) * plane].copy_(x.reshape(-1))
+                st = seg_stages[j] if seg_stages is not None else None
             solver.step(U, V, W, t, float('inf'), rule, cfl, dt_fixed,
-                        dt_used=dts[k:k + 1], alpha_rec=recs[k])
+                        dt_used=dts[k:k + 1], alpha_rec=recs[k], stages=st)
         ctx.solver, ctx.steps, ctx.every = solver, steps, checkpoint_every
         ctx.ckpts, ctx.dts, ctx.recs, ctx.two = ckpts, dts, recs, two
         ctx.store_stages = store_stages
+        ctx.last = (last, n_last, seg_states, seg_stages)
         return (U, V, W) if two else (U, V)
 
     @staticmethod
@@ -49,27 +66,27 @@ class HwenoRollout(torch.autograd.Function):
                for g in grads[:nf]]
         out = [s.new_state() for _ in range(nf)]
         plane = s.prob.ncomp * s.prob.nx * s.prob.ny
-        per_stage = 2 * nf * plane
-        stage_buf = (torch.empty(every, per_stage, dtype=s.prob.dtype, device=s.device)
-                     if ctx.store_stages else None)
-        # step-start states of one segment, each (U, V[, W]) contiguous, so a
-        # step costs one device copy
-        starts = torch.empty(every + 1, nf * plane, dtype=s.prob.dtype, device=s.device)
+        last, n_last, starts, stage_buf = ctx.last
+        ctx.last = None
 
         def fields(k):
             return [starts[k, f * plane:(f + 1) * plane].view(s.prob.shape) for f in range(nf)]
 
         for seg, start in reversed(list(enumerate(range(0, ctx.steps, every)))):
             end = min(start + every, ctx.steps)
-            for dst, src in zip(fields(0), ctx.ckpts[seg]):
-                dst.copy_(src)
-            for k in range(start, end):
-                j = k - start
-                starts[j + 1].copy_(starts[j])
-                X = fields(j + 1)
-                st = stage_buf[j] if stage_buf is not None else None
-                s.step_frozen(X[0], X[1], X[2] if two else None, ctx.dts[k:k + 1], ctx.recs[k],
-                              stages=st)
+            if start != last:
+                # recompute the segment from its checkpoint (the last one is
+                # still held from the forward); each step-start state is
+                # (U, V[, W]) contiguous, so a step costs one device copy
+                for dst, src in zip(fields(0), ctx.ckpts[seg]):
+                    dst.copy_(src)
+                for k in range(start, end):
+                    j = k - start
+                    starts[j + 1].copy_(starts[j])
+                    X = fields(j + 1)
+                    st = stage_buf[j] if stage_buf is not None else None
+                    s.step_frozen(X[0], X[1], X[2] if two else None, ctx.dts[k:k + 1], ctx.recs[k],
+                                  stages=st)
             for k in reversed(range(start, end)):
                 j = k - start
                 X = fields(j)
