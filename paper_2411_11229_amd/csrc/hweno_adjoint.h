@@ -14,7 +14,10 @@ HWENO_HD double sgn0(double x) { return (double)((x > 0.0) - (x < 0.0)); }
 
 // ---------------------------------------------------------------- HWENO point
 // Reverse of hweno_point: given cotangents gR, gL, gT of (uR, uL, vt), adds
-// the cotangents of (um, u0, up, vm, vp).
+// the cotangents of (um, u0, up, vm, vp). Its forward part is written
+// through the candidate values (unscaled weights), so it shares nothing with
+// a forward hweno_point on the same data: the cheaper choice where that
+// forward's intermediates could not stay in registers until the reverse.
 template <typename T>
 HWENO_HD void hweno_point_vjp(T um, T u0, T up, T vm, T vp, const Scheme& s, double h, double ih,
                               double gR, double gL, double gT, T& gum, T& gu0, T& gup, T& gvm,
@@ -115,6 +118,90 @@ HWENO_HD void hweno_point_vjp(T um, T u0, T up, T vm, T vp, const Scheme& s, dou
   gup += (T)rup;
   gvm += (T)rvm;
   gvp += (T)rvp;
+}
+
+// The same reverse for the current hweno_point arithmetic (scaled weights
+// o_l, one division), which also returns the forward values (uR, uL, vt) in
+// fR, fL, fT: when it follows a forward hweno_point on the same data the
+// compiler shares the forward part between the two.
+template <typename T>
+HWENO_HD void hweno_point_vjp_fused(T um, T u0, T up, T vm, T vp, const Scheme& s, double h,
+                                    double ih, double gR, double gL, double gT, T& gum, T& gu0,
+                                    T& gup, T& gvm, T& gvp, T& fR, T& fL, T& fT) {
+  // ---- forward, as hweno_point
+  const double dc = (double)u0;
+  const double e1 = dc - (double)um, e2 = (double)up - dc;
+  const double vmd = (double)vm, vpd = (double)vp;
+  const double cdf = e1 + e2, sdf = e2 - e1;
+  const double qh = 0.25 * h;
+  const double sv = qh * (vmd + vpd), dv = qh * (vmd - vpd);
+  constexpr double r13 = 2.0816659994661326;    // sqrt(13/3)
+  constexpr double r781 = 6.248999919987197;    // sqrt(781/20)
+  constexpr double r1421 = 24.99636017459386;   // sqrt(1421461/2275)
+  constexpr double A1 = r13 * 197.0 / 260.0, A2 = r13 * 67.0 / 130.0;
+  const double t1 = 0.6875 * cdf - 0.75 * sv;
+  const double t2 = A1 * sdf + A2 * dv;
+  const double a3 = r781 * sv - (0.25 * r781) * cdf;
+  const double a4 = (-0.5 * r1421) * sdf - r1421 * dv;
+  const double b0 = t1 * t1 + t2 * t2 + a3 * a3 + a4 * a4;
+  const double b1 = e1 * e1, b2 = e2 * e2;
+  const double d1 = b0 - b1, d2 = b0 - b2;
+  const double ts = fabs(d1) + fabs(d2);
+  const double tau = 0.25 * ts * ts;
+  const double q0 = b0 + s.eps, q1 = b1 + s.eps, q2 = b2 + s.eps;
+  const double p0 = q0 + tau, p1 = q1 + tau, p2 = q2 + tau;
+  const double q12 = q1 * q2, q02 = q0 * q2, q01 = q0 * q1;
+  const double o0 = q12 * p0, o1 = q02 * p1, o2 = q01 * p2;
+  const double o12 = o1 + o2;
+  const double Sg = s.gamma0 * o0 + s.g1 * o12;
+  const double Sd = s.d0 * o0 + s.d1 * o12;
+  const double inv = rcp_nr(Sg * Sd);
+  const double iSg = Sd * inv, iSd = Sg * inv;
+  const double X = o1 * e1 + o2 * e2;
+  const double gX0 = 0.5 * s.g1 * X;
+  const double K = 0.34375 - 0.5 * s.g1;
+  const double base = K * cdf - 0.375 * sv;
+  const double m = 0.21875 * sdf + 0.1875 * dv;
+  const double P1 = o0 * base + gX0, P2 = o0 * m;
+  const double NR = P1 + P2, NL = P1 - P2;
+  const double c3 = (0.75 - s.d1) * ih;
+  const double AT = (0.75 - s.d1) * ih * cdf - ih * sv;
+  const double NT = o0 * AT + s.d1 * ih * X;
+  fR = (T)(dc + NR * iSg);
+  fL = (T)(dc - NL * iSg);
+  fT = (T)(NT * iSd);
+  // ---- reverse
+  const double gNR = gR * iSg, gNL = -gL * iSg, gNT = gT * iSd;
+  const double gSg = -(gNR * NR + gNL * NL) * iSg;
+  const double gSd = -gNT * NT * iSd;
+  const double gsum = gNR + gNL;
+  const double gX = 0.5 * s.g1 * gsum + s.d1 * ih * gNT;
+  const double go0 = gNR * (base + m) + gNL * (base - m) + gNT * AT + s.gamma0 * gSg + s.d0 * gSd;
+  const double go12 = s.g1 * gSg + s.d1 * gSd;
+  const double go1 = go12 + gX * e1, go2 = go12 + gX * e2;
+  const double gbase = o0 * gsum, gm = o0 * (gNR - gNL), gAT = o0 * gNT;
+  // o_l = (product of the other q's) (q_l + tau)
+  const double gp0 = go0 * q12, gp1 = go1 * q02, gp2 = go2 * q01;
+  const double gq0 = gp0 + go1 * q2 * p1 + go2 * q1 * p2;
+  const double gq1 = gp1 + go0 * q2 * p0 + go2 * q0 * p2;
+  const double gq2 = gp2 + go0 * q1 * p0 + go1 * q0 * p1;
+  const double gts = 0.5 * ts * (gp0 + gp1 + gp2);
+  const double gd1 = gts * sgn0(d1), gd2 = gts * sgn0(d2);
+  const double gb0 = gq0 + gd1 + gd2;
+  const double gb1 = gq1 - gd1, gb2 = gq2 - gd2;
+  const double gt1 = 2.0 * t1 * gb0, gt2 = 2.0 * t2 * gb0;
+  const double ga3 = 2.0 * a3 * gb0, ga4 = 2.0 * a4 * gb0;
+  const double gcdf = 0.6875 * gt1 - (0.25 * r781) * ga3 + K * gbase + c3 * gAT;
+  const double gsdf = A1 * gt2 - (0.5 * r1421) * ga4 + 0.21875 * gm;
+  const double gsv = -0.75 * gt1 + r781 * ga3 - 0.375 * gbase - ih * gAT;
+  const double gdv = A2 * gt2 - r1421 * ga4 + 0.1875 * gm;
+  const double ge1 = gX * o1 + 2.0 * e1 * gb1 + gcdf - gsdf;
+  const double ge2 = gX * o2 + 2.0 * e2 * gb2 + gcdf + gsdf;
+  gum += (T)(-ge1);
+  gu0 += (T)(gR + gL + ge1 - ge2);
+  gup += (T)ge2;
+  gvm += (T)(qh * (gsv + gdv));
+  gvp += (T)(qh * (gsv - gdv));
 }
 
 // Reverse of face_derivs: cotangents gR, gL of (vR, vL) -> (um, u0, up, vm, vp).
@@ -407,10 +494,65 @@ HWENO_HD void unproject_vjp(const Euler<DIM>&, const typename Euler<DIM>::templa
   }
 }
 
+// The two parts of unproject_vjp, for use one component at a time.
+// unproject_t: gx += R^T gU (the cotangent of c). unproject_eb: the basis
+// cotangent from component c_j alone (R c is linear in c, so the parts of all
+// components add up to unproject_vjp's). With a = c_0 + c_E, dd = c_E - c_0,
+// s0 = a + c_1: U = (s0, vel s0 + c dd n [+ c_2 t], H a + vn c dd + k c_1
+// [+ vt c_2]).
+template <int D, int DIM, typename T>
+HWENO_HD void unproject_t(const Euler<DIM>&, const typename Euler<DIM>::template Eig<T>& e,
+                          const T (&gU)[DIM + 2], T (&gx)[DIM + 2]) {
+  if constexpr (DIM == 1) {
+    const T gS0 = gU[0] + e.mu * gU[1];
+    const T gdd = e.c * gU[1] + e.mu * e.c * gU[2];
+    const T ga = gS0 + e.H * gU[2];
+    gx[1] += gS0 + e.k * gU[2];
+    gx[0] += ga - gdd;
+    gx[2] += ga + gdd;
+  } else {
+    const T vn = D == 0 ? e.mu : e.nu, vt = D == 0 ? e.nu : e.mu;
+    const T gS0 = gU[0] + e.mu * gU[1] + e.nu * gU[2];
+    const T gUn = D == 0 ? gU[1] : gU[2];
+    const T gUt = D == 0 ? gU[2] : gU[1];
+    const T gdd = e.c * gUn + vn * e.c * gU[3];
+    const T ga = gS0 + e.H * gU[3];
+    gx[1] += gS0 + e.k * gU[3];
+    gx[2] += gUt + vt * gU[3];
+    gx[0] += ga - gdd;
+    gx[3] += ga + gdd;
+  }
+}
+template <int D, int DIM, typename T>
+HWENO_HD void unproject_eb(const Euler<DIM>&, const typename Euler<DIM>::template Eig<T>& e, int j,
+                           T xj, const T (&gU)[DIM + 2], EigBar<T>& eb) {
+  constexpr int E = DIM + 1;
+  const T gUn = (DIM == 1 || D == 0) ? gU[1] : gU[2];
+  const T gUt = DIM == 1 ? T(0) : (D == 0 ? gU[2] : gU[1]);
+  const T vn = D == 0 ? e.mu : e.nu;
+  T gvn = T(0), gvt = T(0);
+  if (j == 0 || j == E) {
+    const T sg = j == 0 ? T(-1) : T(1);   // d dd / d c_j
+    gvn = xj * (gUn + sg * e.c * gU[E]);
+    gvt = xj * gUt;
+    eb.c += sg * xj * (gUn + vn * gU[E]);
+    eb.H += xj * gU[E];
+  } else if (j == 1) {
+    gvn = xj * gUn;
+    gvt = xj * gUt;
+    eb.k += xj * gU[E];
+  } else {   // j == 2 in 2D: the transverse-velocity column
+    gvt = xj * gU[E];
+  }
+  if (D == 0) { eb.mu += gvn; eb.nu += gvt; } else { eb.nu += gvn; eb.mu += gvt; }
+}
+
 // ---------------------------------------------------- one cell's HWENO
 // Reverse of hweno_cell<D>: cotangents (guR, guL, gat) of (uR, uL, v~) ->
-// contributions to the five stencil inputs.
-template <int D, class Sys, typename T>
+// contributions to the five stencil inputs. kFused: through
+// hweno_point_vjp_fused (for callers that ran hweno_cell<D> on the same data
+// just before and can keep its intermediates), else hweno_point_vjp.
+template <int D, bool kFused = false, class Sys, typename T>
 HWENO_HD void hweno_cell_vjp(const Sys& sy, const Scheme& s, double h, double ih,
                              const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
                              const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
@@ -420,8 +562,15 @@ HWENO_HD void hweno_cell_vjp(const Sys& sy, const Scheme& s, double h, double ih
                              T (&gAm)[Sys::NC], T (&gAp)[Sys::NC]) {
   constexpr int NC = Sys::NC;
   if constexpr (!Sys::kChar) {
-    hweno_point_vjp<T>(Um[0], U0[0], Up[0], Am[0], Ap[0], s, h, ih, (double)guR[0],
-                       (double)guL[0], (double)gat[0], gUm[0], gU0[0], gUp[0], gAm[0], gAp[0]);
+    if constexpr (kFused) {
+      T fR, fL, fT;
+      hweno_point_vjp_fused<T>(Um[0], U0[0], Up[0], Am[0], Ap[0], s, h, ih, (double)guR[0],
+                               (double)guL[0], (double)gat[0], gUm[0], gU0[0], gUp[0], gAm[0],
+                               gAp[0], fR, fL, fT);
+    } else {
+      hweno_point_vjp<T>(Um[0], U0[0], Up[0], Am[0], Ap[0], s, h, ih, (double)guR[0],
+                         (double)guL[0], (double)gat[0], gUm[0], gU0[0], gUp[0], gAm[0], gAp[0]);
+    }
   } else {
     const auto q = sy.prim(U0);
     const auto e = sy.eig(q);
@@ -431,23 +580,46 @@ HWENO_HD void hweno_cell_vjp(const Sys& sy, const Scheme& s, double h, double ih
     sy.template project<D>(e, Up, wp);
     sy.template project<D>(e, Am, am);
     sy.template project<D>(e, Ap, ap);
-    T cr[NC], cl[NC], ct[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j)
-      hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, cr[j], cl[j], ct[j]);
     EigBar<T> eb;
-    T gcr[NC], gcl[NC], gct[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) { gcr[j] = T(0); gcl[j] = T(0); gct[j] = T(0); }
-    unproject_vjp<D>(sy, e, cr, guR, eb, gcr);
-    unproject_vjp<D>(sy, e, cl, guL, eb, gcl);
-    unproject_vjp<D>(sy, e, ct, gat, eb, gct);
     T gwm[NC], gw0[NC], gwp[NC], gam[NC], gap[NC];
+    if constexpr (kFused) {
+      // cotangents of the characteristic values first (R^T g needs no
+      // forward values), then each component's reverse, which also returns
+      // its forward values for the basis cotangent
+      T gcr[NC], gcl[NC], gct[NC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0); gam[j] = T(0); gap[j] = T(0);
-      hweno_point_vjp<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, (double)gcr[j],
-                         (double)gcl[j], (double)gct[j], gwm[j], gw0[j], gwp[j], gam[j], gap[j]);
+      for (int j = 0; j < NC; ++j) { gcr[j] = T(0); gcl[j] = T(0); gct[j] = T(0); }
+      unproject_t<D>(sy, e, guR, gcr);
+      unproject_t<D>(sy, e, guL, gcl);
+      unproject_t<D>(sy, e, gat, gct);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0); gam[j] = T(0); gap[j] = T(0);
+        T cr, cl, ct;
+        hweno_point_vjp_fused<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, (double)gcr[j],
+                                 (double)gcl[j], (double)gct[j], gwm[j], gw0[j], gwp[j], gam[j],
+                                 gap[j], cr, cl, ct);
+        unproject_eb<D>(sy, e, j, cr, guR, eb);
+        unproject_eb<D>(sy, e, j, cl, guL, eb);
+        unproject_eb<D>(sy, e, j, ct, gat, eb);
+      }
+    } else {
+      T cr[NC], cl[NC], ct[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, cr[j], cl[j], ct[j]);
+      T gcr[NC], gcl[NC], gct[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) { gcr[j] = T(0); gcl[j] = T(0); gct[j] = T(0); }
+      unproject_vjp<D>(sy, e, cr, guR, eb, gcr);
+      unproject_vjp<D>(sy, e, cl, guL, eb, gcl);
+      unproject_vjp<D>(sy, e, ct, gat, eb, gct);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0); gam[j] = T(0); gap[j] = T(0);
+        hweno_point_vjp<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, (double)gcr[j],
+                           (double)gcl[j], (double)gct[j], gwm[j], gw0[j], gwp[j], gam[j], gap[j]);
+      }
     }
     project_vjp<D>(sy, e, Um, gwm, eb, gUm);
     project_vjp<D>(sy, e, U0, gw0, eb, gU0);

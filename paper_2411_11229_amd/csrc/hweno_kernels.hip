@@ -659,7 +659,7 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     tm[c] = T(0); tc[c] = T(0); tp[c] = T(0); tAm[c] = T(0); tAp[c] = T(0);
     face_derivs_vjp(gvR[c], gvL[c], ih, tm[c], tc[c], tp[c], tAm[c], tAp[c]);
   }
-  hweno_cell_vjp<D>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, guR, guL, aA, tm, tc, tp, tAm, tAp);
+  hweno_cell_vjp<D, true>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, guR, guL, aA, tm, tc, tp, tAm, tAp);
   // ---- gather: own + right-neighbour part of the left lane + left part of the right lane
 #pragma unroll
   for (int c = 0; c < NC; ++c) {

@@ -24,6 +24,25 @@ static std::mt19937_64 rng(20241111);
 static double unif(double a, double b) { return std::uniform_real_distribution<double>(a, b)(rng); }
 static int failures = 0;
 
+// Agreement of two reverse-mode forms of one function (same derivative,
+// different arithmetic), on random cotangents from a generator of their own.
+static std::mt19937_64 rng2(777);
+static void compare(const char* name, int m, const std::function<Vec(const Vec&)>& b1,
+                    const std::function<Vec(const Vec&)>& b2, double tol = 1e-10) {
+  double worst = 0.0;
+  for (int trial = 0; trial < 6; ++trial) {
+    Vec g(m);
+    for (auto& v : g) v = std::uniform_real_distribution<double>(-1, 1)(rng2);
+    const Vec r1 = b1(g), r2 = b2(g);
+    double mag = 1e-300;
+    for (double v : r1) mag = std::max(mag, std::fabs(v));
+    for (size_t i = 0; i < r1.size(); ++i) worst = std::max(worst, std::fabs(r1[i] - r2[i]) / mag);
+  }
+  const bool ok = worst <= tol;
+  if (!ok) ++failures;
+  std::printf("%-44s max rel diff %.2e %s\n", name, worst, ok ? "ok" : "FAIL");
+}
+
 static Scheme scheme(double h, double g0) {
   Scheme s{};
   s.dx = s.dy = h;
@@ -85,6 +104,25 @@ static void check_hweno_point(const char* name, const Vec& x, double h, double g
     return Vec(r, r + 5);
   };
   check(name, x, 3, f, b);
+  // the fused form: the same cotangents, and hweno_point's forward values
+  double worst_fwd = 0.0;
+  const Vec y = f(x);
+  auto bf = [&](const Vec& g) {
+    double r[5] = {0, 0, 0, 0, 0}, fR, fL, fT;
+    hweno_point_vjp_fused<double>(x[0], x[1], x[2], x[3], x[4], s, h, 1.0 / h, g[0], g[1], g[2],
+                                  r[0], r[1], r[2], r[3], r[4], fR, fL, fT);
+    worst_fwd = std::max({worst_fwd, std::fabs(fR - y[0]), std::fabs(fL - y[1]), std::fabs(fT - y[2])});
+    return Vec(r, r + 5);
+  };
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "%s, fused form", name);
+  compare(buf, 3, [&](const Vec& g) { return b(x, g); }, bf);
+  double ymag = 0.0;
+  for (double v : y) ymag = std::max(ymag, std::fabs(v));
+  if (worst_fwd > 1e-14 * ymag) {
+    std::printf("%-44s forward values differ by %.2e FAIL\n", buf, worst_fwd);
+    ++failures;
+  }
 }
 
 // ------------------------------------------------------------ Euler pieces
@@ -148,6 +186,18 @@ static void check_euler(const char* tag) {
     };
     std::snprintf(buf, sizeof buf, "euler%s %s", tag, which == 0 ? "project (L U)" : "unproject (R x)");
     check(buf, x, NC, f, b);
+    if (which == 1) {   // the split form of unproject_vjp, one component at a time
+      auto split = [&](const Vec& gy) {
+        double U[NC], X[NC], gY[NC], gU[NC] = {}, gX[NC] = {}; arr(x, 0, U); arr(x, NC, X); arr(gy, 0, gY);
+        auto q = sy.prim(U); auto e = sy.eig(q); EigBar<double> eb; PrimBar<double> pb;
+        unproject_t<D>(sy, e, gY, gX);
+        for (int j = 0; j < NC; ++j) unproject_eb<D>(sy, e, j, X[j], gY, eb);
+        eig_vjp(sy, q, e, eb, pb); prim_vjp(sy, U, q, pb, gU);
+        Vec r(gU, gU + NC); r.insert(r.end(), gX, gX + NC); return r;
+      };
+      std::snprintf(buf, sizeof buf, "euler%s unproject, split form", tag);
+      compare(buf, NC, [&](const Vec& g) { return b(x, g); }, split);
+    }
   }
   // structured projections equal the explicit rows / columns; L R = I
   {
@@ -217,6 +267,18 @@ static void check_euler(const char* tag) {
     };
     std::snprintf(buf, sizeof buf, "euler%s hweno_cell (%s)", tag, regime == 0 ? "smooth" : regime == 1 ? "jump" : "rough");
     check(buf, x, 3 * NC, f, b, 2e-5);
+    auto bf = [&](const Vec& g) {
+      double Um[NC], U0[NC], Up[NC], Am[NC], Ap[NC], gR[NC], gL[NC], gT[NC];
+      arr(x, 0, Um); arr(x, NC, U0); arr(x, 2 * NC, Up); arr(x, 3 * NC, Am); arr(x, 4 * NC, Ap);
+      arr(g, 0, gR); arr(g, NC, gL); arr(g, 2 * NC, gT);
+      double o[5][NC] = {};
+      hweno_cell_vjp<D, true>(sy, s, h, 1.0 / h, Um, U0, Up, Am, Ap, gR, gL, gT, o[0], o[1], o[2], o[3], o[4]);
+      Vec r;
+      for (int k = 0; k < 5; ++k) r.insert(r.end(), o[k], o[k] + NC);
+      return r;
+    };
+    std::snprintf(buf, sizeof buf, "euler%s hweno_cell fused (%s)", tag, regime == 0 ? "smooth" : regime == 1 ? "jump" : "rough");
+    compare(buf, 3 * NC, [&](const Vec& g) { return b(x, g); }, bf);
   }
 }
 
