@@ -22,7 +22,8 @@
  *   - The caller owns every buffer, including the workspace ws, whose size
  *     comes from hweno_workspace_bytes and which must be passed through
  *     hweno_workspace_init once before first use. The library allocates no
- *     device memory and keeps no global state. Calls on different streams
+ *     device memory and keeps no device state; its only global state is a
+ *     host-side cache of occupancy queries. Calls on different streams
  *     with different workspaces are independent; calls sharing a workspace
  *     must be ordered on one stream.
  *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
@@ -161,14 +162,22 @@ hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void
                                void* ws, hipStream_t stream);
 
 /*
- * Discrete adjoint of one hweno_step (row a12 of the design: derived from
- * (fully-hweno)/(2Dfully-hweno)). Given lambda = dJ/dX^{n+1} (lam_*_in) it
- * writes dJ/dX^n (lam_*_out), where X = (u, v, w), with the recorded dt
- * (device double) and stage alphas (device double[3][2]) held fixed, i.e.
- * not differentiated. (u_n, v_n, w_n) is the step's initial state. `stages`
- * holds X^(1), X^(2) as written by hweno_step, or is NULL, in which case
- * they are recomputed. At the kinks of |beta0 - beta_k| the derivative of
- * |.| is taken as sign(0) = 0. Output buffers must not alias any input.
+ * Discrete adjoint of one hweno_step: the transpose of the Jacobian of the
+ * SSP-RK3 step (fully-hweno)/(2Dfully-hweno), obtained by the chain rule
+ * through every stage. Given lambda = dJ/dX^{n+1} (lam_*_in) it writes
+ * dJ/dX^n (lam_*_out), where X = (u, v, w), with the recorded dt (device
+ * double) and stage alphas (device double[3][2]) held fixed, i.e. not
+ * differentiated. With B(X) = (u, v~(X), w~(X)) the RK base and
+ * vjp(X; a, b) = (dB/dX)^T a + (dL/dX)^T b for one stage:
+ *   lambda2 = vjp(X^(2); 2/3 lambda, 2/3 dt lambda),
+ *   lambda1 = vjp(X^(1); 1/4 lambda2, 1/4 dt lambda2),
+ *   out     = vjp(X^n; lambda1 + 3/4 lambda2 + 1/3 lambda, dt lambda1).
+ * (u_n, v_n, w_n) is the step's initial state. `stages` holds X^(1), X^(2)
+ * as written by hweno_step, or is NULL, in which case they are recomputed
+ * (in the workspace, which also holds lambda2 and lambda1). At the kinks of
+ * |beta0 - beta_k| the derivative of |.| is taken as sign(0) = 0. Output
+ * buffers must not alias any input. The result is deterministic: every sum
+ * is formed in a fixed order, without atomics.
  */
 hweno_status hweno_adjoint_step(const hweno_problem* prob, const void* u_n, const void* v_n,
                                 const void* w_n, const void* stages, const double* dt,
