@@ -690,13 +690,15 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
 }
 
 // y-direction VJP by marching up strips of rows (2D; natural layout, no
-// transposes). Each lane owns one column and needs no neighbour lane. The
-// strip's output rows [o0, o1) are virtual rows in [-2, ny+2): ghost-row
-// results go to a side buffer folded later by ghost_fold_rows_kernel. At
-// iteration r (row r loaded): the interface cotangents of (r-1)+1/2, the
-// reverse of row r-1's HWENO and face values (contributions to rows r-2..r),
-// and the reverse of row r-2's pointwise fluxes; row r-2 is then complete and
-// is added to G (which holds the x-direction result).
+// transposes). Each lane owns one column and needs no neighbour lane. Strip k
+// owns the virtual rows [o0, o1) of [-2, ny+2) and reverses the HWENO of its
+// own cells only: the contributions of cell o0 to row o0-1 and of cell o1-1
+// to row o1 go to a halo buffer, and vjp_y_fold_kernel adds them (and the
+// ghost rows, kept in a side buffer) afterwards. At iteration r (row r
+// loaded): the interface cotangents of (r-1)+1/2, the reverse of cell r-1's
+// HWENO and face values if the strip owns it (contributions to rows r-2..r),
+// and the reverse of row r-2's pointwise fluxes; row r-2 is then complete up
+// to the halo terms and is added to G (which holds the x-direction result).
 template <typename T>
 struct VjpYArgs {
   const T* X[3];          // u, v, w
@@ -709,6 +711,7 @@ struct VjpYArgs {
   const double* alpha;    // [2]; uses alpha[1]
   T* G[3];                // in/out: u, v, w
   T* ghost;               // [4][3][NC][nx]: rows -2, -1, ny, ny+1
+  T* halo;                // [strip][2: to row o0-1, to row o1][2: u, w][NC][nx]
   const T* xghost;        // x-pass ghost columns [ny][4][3][NC], folded here
   int nx, ny, rows, plane;
   int bc_lo, bc_hi;
@@ -770,8 +773,8 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
     T accUc[NC], accWc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) { accUc[c] = T(0); accWc[c] = T(0); }
-    if (r >= o0) {
-      // reverse of row r-1's faces: top face -> interface (r-1)+1/2 (minus
+    if (r >= o0 + 1 && r <= o1) {
+      // reverse of cell r-1's faces: top face -> interface (r-1)+1/2 (minus
       // side), bottom face -> interface (r-2)+1/2 (plus side)
       T uT[NC], uB[NC], wt_[NC], wT[NC], wB[NC];
       hweno_cell<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, uT, uB, wt_);
@@ -814,6 +817,16 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
         accUa[c] += tm[c];
         accWa[c] += tWm[c];
         accUb[c] += tc[c];
+      }
+    }
+    if (r == o0 + 1 && colok) {
+      // row r-2 = o0-1 belongs to the strip below: its sums (from cell o0
+      // alone) leave through the halo buffer
+      T* hb = A.halo + (size_t)blockIdx.y * 4 * NC * A.nx + x;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        hb[(0 * NC + c) * A.nx] = accUa[c];
+        hb[(1 * NC + c) * A.nx] = accWa[c];
       }
     }
     if (r >= o0 + 2) {
@@ -892,23 +905,80 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
       accUb[c] = accUc[c]; accWb[c] = accWc[c];
     }
   }
+  // row o1 belongs to the strip above: its sums (from cell o1-1 alone) leave
+  // through the halo buffer
+  if (colok) {
+    T* hb = A.halo + (size_t)blockIdx.y * 4 * NC * A.nx + x;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      hb[(2 * NC + c) * A.nx] = accUa[c];
+      hb[(3 * NC + c) * A.nx] = accWa[c];
+    }
+  }
 }
 
-// Folds the ghost-row contributions of vjp_y_kernel into the rows they were
-// copied from (one thread per column, field and component; fixed order).
-// Periodic rows map -2, -1, ny, ny+1 to four distinct rows; transmissive rows
-// map the pairs to rows 0 and ny-1 (both sides share one boundary type).
+// Completes vjp_y_kernel's result: adds the halo terms of the strip
+// boundaries and folds the ghost rows into the rows they were copied from.
+// Threads (boundary, column, field, component) add the two halo terms of a
+// boundary whose rows are both in [2, ny-3] (such rows belong to no other
+// boundary and to no ghost image); threads (last slot, column, field,
+// component) handle, in a fixed order, the boundaries near the edges (halo
+// terms aimed at ghost rows go into the ghost side buffer) and then the ghost
+// rows: periodic rows -2, -1, ny, ny+1 map to ny-2, ny-1, 0, 1, transmissive
+// ones to 0, 0, ny-1, ny-1 (both sides share one boundary type). Strip k owns
+// the virtual rows [-2 + k R, -2 + (k+1) R).
 template <typename T>
-__global__ __launch_bounds__(256) void ghost_fold_rows_kernel(T* __restrict__ G0, T* __restrict__ G1,
-                                                              T* __restrict__ G2,
-                                                              const T* __restrict__ ghost, int nx,
-                                                              int ny, int plane, int nc, int periodic) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nx * 3 * nc) return;
-  const int x = t % nx;
-  const int fc = t / nx;            // f * nc + c
+__global__ __launch_bounds__(256) void vjp_y_fold_kernel(T* __restrict__ G0, T* __restrict__ G1,
+                                                         T* __restrict__ G2, T* __restrict__ ghost,
+                                                         const T* __restrict__ halo, int nx, int ny,
+                                                         int plane, int nc, int R, int nstrips,
+                                                         int periodic) {
+  const long per = 3L * nc * nx;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per * nstrips) return;
+  const int k = (int)(t / per);
+  const int rem = (int)(t - (long)k * per);
+  const int x = rem % nx;
+  const int fc = rem / nx;            // f * nc + c
   const int f = fc / nc, c = fc % nc;
   T* G = (f == 0 ? G0 : (f == 1 ? G1 : G2)) + (size_t)c * plane + x;
+  const int hf = f == 0 ? 0 : 1;      // halo field: u or w (v has no halo terms)
+  // halo term of strip j: side 0 -> its row o0-1, side 1 -> its row o1
+  auto hterm = [&](int j, int side) {
+    return halo[(((size_t)j * 4 + side * 2 + hf) * nc + c) * nx + x];
+  };
+  auto edge = [&](int v) { return v < 2 || v > ny - 3; };
+  if (k < nstrips - 1) {
+    // boundary between strips k and k+1: rows a = o1 - 1 (strip k), b = o1
+    const int o1 = -2 + (k + 1) * R;
+    if (f == 1 || edge(o1 - 1) || edge(o1)) return;
+    G[(size_t)(o1 - 1) * nx] += hterm(k + 1, 0);
+    G[(size_t)o1 * nx] += hterm(k, 1);
+    return;
+  }
+  // the edge thread of (column, field, component)
+  if (f != 1) {
+    auto add = [&](int v, T val) {
+      if (v >= 0 && v < ny) {
+        G[(size_t)v * nx] += val;
+      } else {
+        const int slot = v < 0 ? v + 2 : v - ny + 2;
+        ghost[((size_t)slot * 3 * nc + fc) * nx + x] += val;
+      }
+    };
+    // edge boundaries: o1 <= 2 at the bottom, o1 > ny - 3 at the top
+    int j = 0;
+    for (; j < nstrips - 1 && -2 + (j + 1) * R <= 2; ++j) {
+      const int o1 = -2 + (j + 1) * R;
+      add(o1 - 1, hterm(j + 1, 0));
+      add(o1, hterm(j, 1));
+    }
+    for (j = max(j, (ny - 1) / R); j < nstrips - 1; ++j) {
+      const int o1 = -2 + (j + 1) * R;
+      add(o1 - 1, hterm(j + 1, 0));
+      add(o1, hterm(j, 1));
+    }
+  }
   const size_t gs = (size_t)3 * nc * nx;
   const T* gp = ghost + (size_t)fc * nx + x;
   const T g0 = gp[0], g1 = gp[gs], g2 = gp[2 * gs], g3 = gp[3 * gs];
@@ -1016,8 +1086,8 @@ Geometry geometry(const hweno_problem* p) {
 // Workspace: scalars | per-block partial maxima | states | adjoint scratch.
 // States are stored densely ([field][comp][ny][nx]); each region starts on a
 // 256-byte boundary. Regions: X^(1), X^(2), the RK base derivatives
-// (V~^n[, W~^n]), and for the adjoint: lambda^(2), lambda^(1) and the
-// ghost-cell side buffer.
+// (V~^n[, W~^n]), and for the adjoint: lambda^(2), lambda^(1), the
+// ghost-cell side buffers and (2D) the y-pass strip halo terms.
 struct WsLayout {
   StepScalars* sc;
   double* partial;
@@ -1028,6 +1098,7 @@ struct WsLayout {
   char* lam1;
   char* ghost;     // x-pass ghost columns [ny][4][3][NC]
   char* ghost_y;   // y-pass ghost rows [4][3][NC][nx]
+  char* halo;      // y-pass strip halo terms [strips][2][2][NC][nx]
   size_t state_bytes;
 };
 
@@ -1039,7 +1110,16 @@ size_t ghost_x_bytes(const hweno_problem* p, const Geometry& g) {
 size_t ghost_y_bytes(const hweno_problem* p, const Geometry& g) {
   return p->dim == 2 ? align_up((size_t)p->nx * 4 * 3 * g.nc * g.esize, 256) : 0;
 }
-size_t ghost_bytes(const hweno_problem* p, const Geometry& g) { return ghost_x_bytes(p, g) + ghost_y_bytes(p, g); }
+// y-VJP strips have at least kMinStripRows of the ny + 4 virtual rows
+constexpr int kMinStripRows = 4;
+size_t halo_bytes(const hweno_problem* p, const Geometry& g) {
+  if (p->dim != 2) return 0;
+  const size_t strips = (size_t)(p->ny + 4 + kMinStripRows - 1) / kMinStripRows;
+  return align_up(strips * 4 * g.nc * (size_t)p->nx * g.esize, 256);
+}
+size_t ghost_bytes(const hweno_problem* p, const Geometry& g) {
+  return ghost_x_bytes(p, g) + ghost_y_bytes(p, g) + halo_bytes(p, g);
+}
 size_t ws_total(const hweno_problem* p, const Geometry& g) {
   return kScalarBytes + kPartialBytes + 4 * state_bytes(g) + base_bytes(g) + ghost_bytes(p, g);
 }
@@ -1057,6 +1137,7 @@ WsLayout ws_layout(const hweno_problem* p, void* ws, const Geometry& g) {
   w.lam1 = w.lam2 + w.state_bytes;
   w.ghost = w.lam1 + w.state_bytes;
   w.ghost_y = w.ghost + ghost_x_bytes(p, g);
+  w.halo = w.ghost_y + ghost_y_bytes(p, g);
   return w;
 }
 
@@ -1102,62 +1183,47 @@ hweno_status dispatch(const hweno_problem* p, F&& f) {
   return p->precision == HWENO_F64 ? by_type(double{}) : by_type(float{});
 }
 
-// Strip height of the 2D marcher: enough row-blocks to fill whole rounds of
-// resident waves (CUs x waves per CU the kernel's registers and LDS allow),
-// so no round runs nearly empty; long strips also amortise the 4 warm-up
-// rows. At least 8 rows.
-template <class K>
-int strip_rows(K kernel, int mode, int nx, int ny) {
-  static std::atomic<int> per_cu_cache[4];   // per stage mode; 0 = not yet queried
-  int per_cu = per_cu_cache[mode].load(std::memory_order_relaxed);
-  if (per_cu <= 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
-        per_cu <= 0)
-      return 32;
-    per_cu_cache[mode].store(per_cu, std::memory_order_relaxed);
+// Occupancy of `kernel` (block size BLOCK) on the current device: blocks per
+// CU from the occupancy query (cached per kernel instance and TAG) and the CU
+// count (asked each time). False if unknown.
+template <int TAG, int BLOCK, class K>
+bool occupancy(K kernel, int* per_cu, int* cus) {
+  static std::atomic<int> per_cu_cache{0};
+  int pc = per_cu_cache.load(std::memory_order_relaxed);
+  if (pc <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kernel, BLOCK, 0) != hipSuccess || pc <= 0)
+      return false;
+    per_cu_cache.store(pc, std::memory_order_relaxed);
   }
-  int dev = 0, cus = 0;
+  int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    return 32;
-  const long cb = (nx + kXOut - 1) / kXOut;
-  const long slots = (long)cus * per_cu;
-  long rb = slots / cb;
-  if (rb < 1) rb = 1;
-  long rounds = 1;
-  int rows = (int)((ny + rb * rounds - 1) / (rb * rounds));
-  return rows < 8 ? 8 : rows;
+      hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || *cus <= 0)
+    return false;
+  *per_cu = pc;
+  return true;
 }
 
-// Strip height of the y-direction VJP marcher: blocks of 64 columns march
-// up strips of R of the `rows` virtual rows. A strip costs about R + 2.5 row
-// units (two extra HWENO reverses and two load-only rows), and the resident
-// waves (CUs x blocks per CU) run the blocks in rounds of equal length, so
-// R minimises rounds(R) * (R + 2.5).
-template <int TAG, class K>
-int vjp_strip_rows(K kernel, int nx, int rows) {
-  static std::atomic<int> per_cu_cache{0};   // one per kernel instance (TAG)
-  int per_cu = per_cu_cache.load(std::memory_order_relaxed);
-  if (per_cu <= 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
-        per_cu <= 0)
-      return 16;
-    per_cu_cache.store(per_cu, std::memory_order_relaxed);
-  }
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    return 16;
-  const long cb = (nx + kWave - 1) / kWave;
-  const long slots = (long)cus * per_cu;
-  int best = rows;
+// Strip height R of a one-wavefront-per-block marcher: col_blocks blocks side
+// by side, each marching strips of R of `rows` rows. A strip costs R +
+// overhead row units (its warm-up rows). With k of its blocks per SIMD a
+// round of 4 CUs k blocks takes k (R + overhead) / g(k), g(1) = 1 and g(k>1)
+// = 1.1 (the measured gain of a second wavefront on a SIMD in these
+// VALU-bound kernels); R minimises the total over rounds. `fallback` if the
+// occupancy is unknown.
+int balanced_rows(long col_blocks, int rows, bool known, int per_cu, int cus, double overhead,
+                  int fallback, int rmin = 1) {
+  if (!known) return fallback < rmin ? rmin : fallback;
+  const long simds = 4L * cus;
+  const long lanes = per_cu >= 4 ? simds : (long)cus * per_cu;   // blocks at one per SIMD
+  const long kmax = per_cu >= 4 ? per_cu / 4 : 1;
+  int best = rows > rmin ? rows : rmin;
   double best_cost = 1e300;
-  for (int r = 1; r <= rows; ++r) {
-    const long blocks = cb * ((rows + r - 1) / r);
-    const long rounds = (blocks + slots - 1) / slots;
-    const double cost = (double)rounds * (r + 2.5);
+  for (int r = rmin; r <= rows; ++r) {
+    const long blocks = col_blocks * ((rows + r - 1) / r);
+    long k = (blocks + lanes - 1) / lanes;
+    if (k > kmax) k = kmax;
+    const long rounds = (blocks + lanes * k - 1) / (lanes * k);
+    const double cost = (double)rounds * k * (r + overhead) / (k > 1 ? 1.1 : 1.0);
     if (cost < best_cost) {
       best_cost = cost;
       best = r;
@@ -1165,6 +1231,7 @@ int vjp_strip_rows(K kernel, int nx, int rows) {
   }
   return best;
 }
+
 
 template <class Sys, typename T, int DIM>
 hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipStream_t st) {
@@ -1178,16 +1245,20 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
       default: stage1d_kernel<Sys, T, kStage3><<<grid, kWave, 0, st>>>(A, sy); break;
     }
   } else {
-    auto go = [&](auto kernel) {
-      A.rows = strip_rows(kernel, mode, A.nx, A.ny);
+    auto go = [&](auto kernel, auto tag) {
+      int per_cu = 0, cus = 0;
+      const bool known = occupancy<decltype(tag)::value, kWave>(kernel, &per_cu, &cus);
+      // warm-up: two rows of loads and y-pointwise fluxes, two of y-HWENO,
+      // about one full row in all
+      A.rows = balanced_rows((A.nx + kXOut - 1) / kXOut, A.ny, known, per_cu, cus, 1.0, 32);
       dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
       kernel<<<grid, kWave, 0, st>>>(A, sy);
     };
     switch (mode) {
-      case kRhs: go(stage2d_kernel<Sys, T, kRhs>); break;
-      case kStage1: go(stage2d_kernel<Sys, T, kStage1>); break;
-      case kStage2: go(stage2d_kernel<Sys, T, kStage2>); break;
-      default: go(stage2d_kernel<Sys, T, kStage3>); break;
+      case kRhs: go(stage2d_kernel<Sys, T, kRhs>, std::integral_constant<int, kRhs>{}); break;
+      case kStage1: go(stage2d_kernel<Sys, T, kStage1>, std::integral_constant<int, kStage1>{}); break;
+      case kStage2: go(stage2d_kernel<Sys, T, kStage2>, std::integral_constant<int, kStage2>{}); break;
+      default: go(stage2d_kernel<Sys, T, kStage3>, std::integral_constant<int, kStage3>{}); break;
     }
   }
   return check_launch();
@@ -1296,6 +1367,7 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.alpha = alpha;
     for (int f = 0; f < 3; ++f) A.G[f] = out[f];
     A.ghost = (T*)wl.ghost_y;
+    A.halo = (T*)wl.halo;
     A.xghost = (const T*)wl.ghost;
     A.nx = nx;
     A.ny = ny;
@@ -1304,16 +1376,20 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.bc_hi = p->bc[3];
     A.x_periodic = p->bc[0] == HWENO_PERIODIC;
     A.s = sc;
-    auto go = [&](auto kernel, int rows) {
-      A.rows = rows;
-      dim3 grid((nx + kWave - 1) / kWave, (ny + 4 + A.rows - 1) / A.rows);
-      kernel<<<grid, kWave, 0, st>>>(A, sy);
-    };
-    go(vjp_y_kernel<Sys, T>, vjp_strip_rows<0>(vjp_y_kernel<Sys, T>, nx, ny + 4));
+    // strips of at least kMinStripRows rows (the halo buffer is sized for
+    // that); warm-up: four rows of loads
+    int per_cu = 0, cus = 0;
+    const bool known = occupancy<4, kWave>(vjp_y_kernel<Sys, T>, &per_cu, &cus);
+    A.rows = balanced_rows((nx + kWave - 1) / kWave, ny + 4, known, per_cu, cus, 1.0, 16,
+                           kMinStripRows);
+    const int nstrips = (ny + 4 + A.rows - 1) / A.rows;
+    dim3 grid((nx + kWave - 1) / kWave, nstrips);
+    vjp_y_kernel<Sys, T><<<grid, kWave, 0, st>>>(A, sy);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    const int tot = nx * 3 * NC;
-    ghost_fold_rows_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost_y,
-                                                               nx, ny, plane, NC, p->bc[2] == HWENO_PERIODIC);
+    const long tot = 3L * NC * nx * nstrips;
+    vjp_y_fold_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
+        out[0], out[1], out[2], (T*)wl.ghost_y, (const T*)wl.halo, nx, ny, plane, NC, A.rows, nstrips,
+        p->bc[2] == HWENO_PERIODIC);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
   }
   return HWENO_OK;
