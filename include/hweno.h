@@ -152,14 +152,17 @@ hweno_status hweno_step_profiled(const hweno_problem* prob, void* u, void* v, vo
                                  void* ws, hipStream_t stream, hipEvent_t* events);
 
 /*
- * One SSP-RK3 step in place on (u, v, w) with a given time step (device
- * double) and given stage alphas (device double[3][2], e.g. the alpha_rec
- * of an earlier hweno_step): the map whose Jacobian hweno_adjoint_step
- * transposes. No clipping, no time update. `stages` as in hweno_step.
+ * One SSP-RK3 step on (u, v, w) with a given time step (device double) and
+ * given stage alphas (device double[3][2], e.g. the alpha_rec of an earlier
+ * hweno_step): the map whose Jacobian hweno_adjoint_step transposes. No
+ * clipping, no time update. The new state goes to (u_out, v_out, w_out) if
+ * u_out is not NULL (then (u, v, w) are left unchanged and the outputs must
+ * not overlap any input), else in place. `stages` as in hweno_step.
  */
 hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void* w,
-                               const double* dt, const double* alpha_rec, void* stages,
-                               void* ws, hipStream_t stream);
+                               void* u_out, void* v_out, void* w_out, const double* dt,
+                               const double* alpha_rec, void* stages, void* ws,
+                               hipStream_t stream);
 
 /*
  * Discrete adjoint of one hweno_step: the transpose of the Jacobian of the

@@ -1566,13 +1566,23 @@ hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void*
   });
 }
 
-hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w, const double* dt,
-                               const double* alpha_rec, void* stages, void* ws, hipStream_t stream) {
+hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w, void* u_out,
+                               void* v_out, void* w_out, const double* dt, const double* alpha_rec,
+                               void* stages, void* ws, hipStream_t stream) {
   hweno_status st = validate(p);
   if (st != HWENO_OK) return st;
   if (!u || !v || !dt || !alpha_rec || !ws) return HWENO_EINVAL;
   if (p->dim == 2 && !w) return HWENO_EINVAL;
   if (p->dim == 1 && w) return HWENO_EINVAL;
+  if (u_out) {
+    if (!v_out || (p->dim == 2) != (w_out != nullptr)) return HWENO_EINVAL;
+    const void* ins[4] = {u, v, w, stages};
+    for (const void* o : {(const void*)u_out, (const void*)v_out, (const void*)w_out})
+      for (const void* i : ins)
+        if (o && i && o == i) return HWENO_EINVAL;
+  } else if (v_out || w_out) {
+    return HWENO_EINVAL;
+  }
   const Geometry g = geometry(p);
   WsLayout wl = ws_layout(p, ws, g);
   return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
@@ -1600,7 +1610,11 @@ hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w
     A.alpha = alpha_rec + 2;
     if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
     A.U = F(x2, 0); A.V = F(x2, 1); A.W = DIM == 2 ? F(x2, 2) : nullptr;
-    A.Uo = (T*)u; A.Vo = (T*)v; A.Wo = (T*)w;
+    if (u_out) {
+      A.Uo = (T*)u_out; A.Vo = (T*)v_out; A.Wo = (T*)w_out;
+    } else {
+      A.Uo = (T*)u; A.Vo = (T*)v; A.Wo = (T*)w;
+    }
     A.alpha = alpha_rec + 4;
     return launch_stage<Sys, T, DIM>(kStage3, A, sy, stream);
   });

@@ -52,7 +52,7 @@ _SIGS = {
     'hweno_step_profiled': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P],
                             ctypes.c_int),
-    'hweno_step_frozen': ([ctypes.POINTER(_CProblem)] + [_P] * 8, ctypes.c_int),
+    'hweno_step_frozen': ([ctypes.POINTER(_CProblem)] + [_P] * 11, ctypes.c_int),
     'hweno_adjoint_step': ([ctypes.POINTER(_CProblem)] + [_P] * 14, ctypes.c_int),
     'hweno_health': ([ctypes.POINTER(_CProblem), _P, _P, ctypes.c_int32], ctypes.c_int),
 }
@@ -244,15 +244,22 @@ class Solver:
                     and x.is_contiguous() and x.device.type == 'cuda'):
                 raise ValueError(f'{name} must be a contiguous float64 device tensor')
 
-    def step_frozen(self, U, V, W, dt, alpha_rec, stages=None):
-        """One step in place with the given dt (device, 1 value) and stage
-        alphas (device, 6 values): the map the adjoint differentiates."""
+    def step_frozen(self, U, V, W, dt, alpha_rec, stages=None, out=None):
+        """One step with the given dt (device, 1 value) and stage alphas
+        (device, 6 values): the map the adjoint differentiates. In place, or
+        into ``out`` = (U', V'[, W']) leaving (U, V, W) unchanged."""
         two = self.prob.dim == 2
         U, V = self._state(U, 'U'), self._state(V, 'V')
         W = self._state(W, 'W') if two else None
         self._scalars_ok(dt, alpha_rec)
+        o = [None, None, None]
+        if out is not None:
+            if len(out) != (3 if two else 2):
+                raise ValueError('out: one tensor per field')
+            o = [self._state(x, 'out') for x in out] + ([None] if not two else [])
         _check(self.lib.hweno_step_frozen(ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W),
-                                          _ptr(dt), _ptr(alpha_rec), _ptr(self._stages_ok(stages)),
+                                          _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), _ptr(dt),
+                                          _ptr(alpha_rec), _ptr(self._stages_ok(stages)),
                                           _ptr(self.ws), _stream(self.device)), 'hweno_step_frozen')
 
     def adjoint_step(self, U, V, W, dt, alpha_rec, lam_in, lam_out, stages=None):

@@ -76,17 +76,16 @@ class HwenoRollout(torch.autograd.Function):
             end = min(start + every, ctx.steps)
             if start != last:
                 # recompute the segment from its checkpoint (the last one is
-                # still held from the forward); each step-start state is
-                # (U, V[, W]) contiguous, so a step costs one device copy
+                # still held from the forward); each step writes the next
+                # step-start state out of place
                 for dst, src in zip(fields(0), ctx.ckpts[seg]):
                     dst.copy_(src)
                 for k in range(start, end):
                     j = k - start
-                    starts[j + 1].copy_(starts[j])
-                    X = fields(j + 1)
+                    X = fields(j)
                     st = stage_buf[j] if stage_buf is not None else None
                     s.step_frozen(X[0], X[1], X[2] if two else None, ctx.dts[k:k + 1], ctx.recs[k],
-                                  stages=st)
+                                  stages=st, out=fields(j + 1))
             for k in reversed(range(start, end)):
                 j = k - start
                 X = fields(j)

@@ -103,3 +103,20 @@ def test_1d_rejects_w_buffers(lib):
 def test_status_strings(lib):
     for code, text in H.STATUS.items():
         assert lib.hweno_status_string(code).decode().startswith(text.split()[0])
+
+
+def test_frozen_step_output_checks(lib):
+    """hweno_step_frozen's out-of-place form rejects aliasing and partial
+    output sets before launching anything (distinct fake addresses, never
+    dereferenced)."""
+    p = _prob()
+    a = [ctypes.c_void_p(0x1000 * (k + 1)) for k in range(8)]
+    u, v, w, dt, rec, ws = a[0], a[1], a[2], a[3], a[4], a[5]
+    f = lib.hweno_step_frozen
+    # output aliases an input
+    assert f(ctypes.byref(p), u, v, w, u, a[6], a[7], dt, rec, None, ws, None) == -1
+    assert f(ctypes.byref(p), u, v, w, a[6], a[7], v, dt, rec, None, ws, None) == -1
+    # u_out without v_out / w_out, or v_out without u_out
+    assert f(ctypes.byref(p), u, v, w, a[6], None, a[7], dt, rec, None, ws, None) == -1
+    assert f(ctypes.byref(p), u, v, w, a[6], a[7], None, dt, rec, None, ws, None) == -1
+    assert f(ctypes.byref(p), u, v, w, None, a[6], None, dt, rec, None, ws, None) == -1

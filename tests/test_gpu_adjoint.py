@@ -103,6 +103,14 @@ def test_adjoint_step_matches_finite_differences(name, mk):
     # the frozen step reproduces the recorded step
     for a, b in zip(Ys, Y):
         assert torch.equal(a, b)
+    # out of place: the same new state, the input untouched
+    Xc = [x.clone() for x in X]
+    Yo = [torch.empty_like(x) for x in X]
+    s.step_frozen(Xc[0], Xc[1], Xc[2] if two else None, dt, rec, out=Yo)
+    for a, b in zip(Yo, Y):
+        assert torch.equal(a, b)
+    for a, b in zip(Xc, X):
+        assert torch.equal(a, b)
     adj = sum(float((o * d).sum()) for o, d in zip(out, delta))
 
     def D(e):
