@@ -152,9 +152,9 @@ def time_adjoint(precision, n=512, steps=200, every=20):
     return dict(forward_s=fwd, backward_s=bwd, ratio=bwd / fwd, grads_finite=ok)
 
 
-def cpu_baseline(n=512, steps=2, seed=4000):
+def cpu_baseline(n=1024, steps=2, seed=4000):
     """The FP64 oracle (unchanged) on a bounded sample: the same four-quadrant
-    generator at n x n, `steps` SSP-RK3 steps, one thread."""
+    generator at n x n, `steps` SSP-RK3 steps, one thread (about 20 s)."""
     from oracle import hweno as O
     from paper_2411_11229_amd import workloads
     try:
