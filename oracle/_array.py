@@ -53,6 +53,10 @@ class _NP:
     def zeros_like(a):
         return np.zeros_like(a)
 
+    @staticmethod
+    def const(c, like):
+        return np.asarray(c, dtype=np.float64)
+
 
 class _TORCH:
     float64 = None if torch is None else torch.float64
@@ -89,6 +93,10 @@ class _TORCH:
     @staticmethod
     def zeros_like(a):
         return torch.zeros_like(a)
+
+    @staticmethod
+    def const(c, like):
+        return torch.as_tensor(c, dtype=like.dtype)
 
 
 def ns(a):

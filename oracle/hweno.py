@@ -32,9 +32,13 @@ notes of the repository):
     and L = R^{-1}. D(f), D(h), LF and the mixed fluxes act component-wise.
   * Transmissive boundary: zero-order extrapolation of U, V and W into the two
     ghost cells.
+  * Reflective boundary (Euler only): mirror cells with the sign rules of
+    (RBC-1d), (RBC-2d-x), (RBC-2d-y); ghost -1-k is the image of cell k.
 """
 import math
 from dataclasses import dataclass, field
+
+import numpy as np
 
 from . import _array
 
@@ -232,25 +236,65 @@ def make_system(prob):
 # ----------------------------------------------------------------------------
 # Boundary: ghost cells by index map
 # ----------------------------------------------------------------------------
-def pad(a, bc_lo, bc_hi, axis=-1):
-    """Add NG ghost cells on both ends of ``axis``. 'periodic' wraps;
-    'transmissive' copies the nearest interior cell (zero-order extrapolation
-    of U and of its derivatives)."""
+# Reflective walls, remarks of sections 2 and 3 (RBC-1d), (RBC-2d-x),
+# (RBC-2d-y): the ghost state is the mirror image of the interior about the
+# wall, with the normal momentum negated; a derivative along the wall normal
+# changes sign once more, a derivative along the wall does not. Per-component
+# signs of (U, V = U_x, W = U_y) for a wall normal to direction d (Euler only;
+# the paper states no reflective rule for the scalar laws).
+REFLECT_SIGNS = {
+    (1, 0): ((1.0, -1.0, 1.0), (-1.0, 1.0, -1.0), None),                    # (RBC-1d)
+    (2, 0): ((1.0, -1.0, 1.0, 1.0), (-1.0, 1.0, -1.0, -1.0), (1.0, -1.0, 1.0, 1.0)),   # (RBC-2d-x)
+    (2, 1): ((1.0, 1.0, -1.0, 1.0), (1.0, 1.0, -1.0, 1.0), (-1.0, -1.0, 1.0, -1.0)),  # (RBC-2d-y)
+}
+
+
+def reflect_signs(sys, d):
+    """Signs of (U, along-derivative, other derivative) at a wall normal to
+    direction d, in the order ``sweep`` receives its arrays: the along
+    derivative is V for x-walls and W for y-walls. None for scalar laws."""
+    if not isinstance(sys, Euler):
+        return None, None, None
+    sU, sV, sW = REFLECT_SIGNS[(sys.dim, d)]
+    return (sU, sV, sW) if d == 0 else (sU, sW, sV)
+
+
+def pad(a, bc_lo, bc_hi, axis=-1, sign=None):
+    """Add NG ghost cells on both ends of ``axis`` (the last one for the
+    reflective rule). 'periodic' wraps; 'transmissive' copies the nearest
+    interior cell (zero-order extrapolation of U and of its derivatives);
+    'reflective' takes the mirror cell (ghost -1-k is the image of cell k,
+    ghost n+k of cell n-1-k) with component c multiplied by sign[c]."""
     xp = _array.ns(a)
     n = a.shape[axis]
-    idx = []
+    idx, flip = [], []
     for i in range(-NG, n + NG):
         if 0 <= i < n:
             idx.append(i)
+            flip.append(False)
+            continue
+        side = bc_lo if i < 0 else bc_hi
+        if side == 'periodic':
+            idx.append(i % n)
+        elif side == 'transmissive':
+            idx.append(min(max(i, 0), n - 1))
+        elif side == 'reflective':
+            if sign is None:
+                raise ValueError('reflective walls are defined for the Euler equations only')
+            idx.append(-1 - i if i < 0 else 2 * n - 1 - i)
         else:
-            side = bc_lo if i < 0 else bc_hi
-            if side == 'periodic':
-                idx.append(i % n)
-            elif side == 'transmissive':
-                idx.append(min(max(i, 0), n - 1))
-            else:
-                raise ValueError(side)
-    return xp.take(a, idx, axis)
+            raise ValueError(side)
+        flip.append(side == 'reflective')
+    out = xp.take(a, idx, axis)
+    if not any(flip):
+        return out
+    assert axis in (-1, a.ndim - 1)
+    fac = np.ones((a.shape[0], len(idx)))
+    for j, f in enumerate(flip):
+        if f:
+            fac[:, j] = sign
+    fac = fac.reshape((a.shape[0],) + (1,) * (a.ndim - 2) + (len(idx),))
+    return out * xp.const(fac, a)
 
 
 # ----------------------------------------------------------------------------
@@ -376,8 +420,9 @@ def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps):
     """
     xp = _array.ns(U)
     n = U.shape[-1]
-    Up = pad(U, bc_lo, bc_hi)
-    Ap = pad(A, bc_lo, bc_hi)
+    sU, sA, sB = reflect_signs(sys, d)
+    Up = pad(U, bc_lo, bc_hi, sign=sU)
+    Ap = pad(A, bc_lo, bc_hi, sign=sA)
     # HWENO on cells -1..n (padded 1..n+2): interfaces -1/2..n-1/2 need them
     m, c, p = (slice(0, n + 2), slice(1, n + 3), slice(2, n + 4))
     Um, U0, Upl = Up[..., m], Up[..., c], Up[..., p]
@@ -410,7 +455,7 @@ def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps):
     RA = -(Hh[..., 1:] - Hh[..., :-1]) / h
     RB = None
     if B is not None:
-        Bp = pad(B, bc_lo, bc_hi)
+        Bp = pad(B, bc_lo, bc_hi, sign=sB)
         e = sys.jac_apply(Up, Bp, d)
         Eh = mixed_flux(e[..., q[0]], e[..., q[1]], e[..., q[2]], e[..., q[3]])
         RB = -(Eh[..., 1:] - Eh[..., :-1]) / h

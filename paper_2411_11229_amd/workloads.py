@@ -18,6 +18,9 @@ stand-ins with the shapes and value ranges of its examples):
   * ``euler2d_smooth``   2D Euler, seeded smooth Fourier-mode perturbations.
   * ``euler2d_quadrants`` 2D Euler, seeded four-quadrant Riemann data.
   * ``mach2000_initial`` the initial state of Example 4.10 (time-step pin).
+  * ``blast_wave_1d``    Example 4.4 (Woodward-Colella blast waves between
+    two reflective walls).
+  * ``with_bc``          any of the above with other boundary conditions.
 """
 import math
 from dataclasses import dataclass, field
@@ -121,6 +124,26 @@ def mach2000_initial(nx=640, ny=320, g=5.0 / 3.0):
     U, V = conserved_2d(rho, zero, zero, 0.4127 + zero, zero, zero, zero, zero, g)
     return Workload('mach2000', 2, 'euler', nx, ny, hx, hy, U, V, V.copy(),
                     bc=('transmissive',) * 4, gas_gamma=g, x=x, y=y)
+
+
+def blast_wave_1d(n=800, g=1.4):
+    """Example 4.4: (rho, u, P) = (1, 0, 1000) on [0, 0.1), (1, 0, 0.01) on
+    [0.1, 0.9), (1, 0, 100) on [0.9, 1]; reflective walls at both ends;
+    T = 0.038. Piecewise constant, so V = 0."""
+    x, h = centres(n, 0.0, 1.0)
+    p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+    one, zero = np.ones_like(x), np.zeros_like(x)
+    U, V = conserved_1d(one, zero, p, zero, zero, zero, g)
+    return Workload('blast_wave_1d', 1, 'euler', n, 1, h, 1.0, U, V, None,
+                    bc=('reflective', 'reflective', 'periodic', 'periodic'), gas_gamma=g,
+                    t_end=0.038, x=x)
+
+
+def with_bc(w, bc):
+    """A copy of workload ``w`` with boundary conditions ``bc`` (x_lo, x_hi,
+    y_lo, y_hi); the data are unchanged."""
+    import dataclasses
+    return dataclasses.replace(w, bc=tuple(bc), name=f'{w.name}[{",".join(b[0] for b in bc)}]')
 
 
 # ---------------------------------------------------------------- seeded configs

@@ -15,8 +15,14 @@ from paper_2411_11229_amd import workloads as WL
 def _setup(kind):
     if kind == 'euler2d':
         w = WL.euler2d_smooth(10, seed=3100, ny=9)
+    elif kind == 'euler2d-reflective':
+        w = WL.with_bc(WL.euler2d_smooth(10, seed=3102, ny=9),
+                       ('reflective', 'transmissive', 'reflective', 'reflective'))
     elif kind == 'euler1d':
         w = WL.euler1d_riemann_sine(24, seed=2010)
+    elif kind == 'euler1d-reflective':
+        w = WL.with_bc(WL.euler1d_riemann_sine(24, seed=2011),
+                       ('reflective', 'reflective', 'periodic', 'periodic'))
     else:
         w = WL.paper_burgers2d(8)
     p = O.Problem(**w.problem_kwargs())
@@ -29,7 +35,8 @@ def _loss(p, w, log, U, V, W, target):
     return 0.5 * ((Ue - target) ** 2).sum() * p.dx * (p.dy if p.dim == 2 else 1.0)
 
 
-@pytest.mark.parametrize("kind", ["euler1d", "euler2d", "burgers2d"])
+@pytest.mark.parametrize("kind", ["euler1d", "euler1d-reflective", "euler2d",
+                                  "euler2d-reflective", "burgers2d"])
 def test_torch_oracle_gradient_matches_finite_differences(kind):
     w, p, log = _setup(kind)
     rng = np.random.default_rng(5)
