@@ -55,7 +55,18 @@ typedef enum {
 } hweno_status;
 
 typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_system;
-typedef enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1 } hweno_bc;
+/* Boundary conditions, by ghost cells (2 per side):
+ *   periodic      wraps; must be set on both ends of an axis;
+ *   transmissive  copies the nearest interior u, v, w (zero-order
+ *                 extrapolation; the paper states no rule, this is a reading);
+ *   reflective    a wall (remarks on boundary conditions in sections 2 and 3,
+ *                 (RBC-1d), (RBC-2d-x), (RBC-2d-y)): ghost -1-k holds the
+ *                 mirror image of cell k (ghost n+k of cell n-1-k) with the
+ *                 normal momentum negated; the derivative along the wall
+ *                 normal has every other component negated, the derivative
+ *                 along the wall follows the state. HWENO_EULER only.
+ * The two ends of an axis are independent except for periodic. */
+typedef enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2 } hweno_bc;
 typedef enum { HWENO_F64 = 0, HWENO_F32 = 1 } hweno_precision;
 typedef enum {
   HWENO_DT_PRODUCTION = 0,   /* dt = cfl / (ax/dx + ay/dy)                    */
@@ -82,9 +93,7 @@ typedef struct {
   double gamma0;        /* in (0, 1)                                              */
   double d0;            /* in (0, 1)                                              */
   double eps;           /* > 0                                                    */
-  int32_t bc[4];        /* hweno_bc at x_lo, x_hi, y_lo, y_hi. Periodic must be  */
-                        /* set on both ends of an axis. Transmissive copies the  */
-                        /* nearest interior u, v, w into the 2 ghost cells.      */
+  int32_t bc[4];        /* hweno_bc at x_lo, x_hi, y_lo, y_hi (see hweno_bc)      */
   int32_t precision;    /* hweno_precision of every array argument                */
 } hweno_problem;
 

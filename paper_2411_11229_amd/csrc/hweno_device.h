@@ -547,16 +547,60 @@ HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
 }
 
 // ------------------------------------------------------------- index maps
+// Boundary codes, as in the C ABI.
+constexpr int kBcPeriodic = 0, kBcTransmissive = 1, kBcReflective = 2;
+
 // Ghost cells by index map: periodic wraps, transmissive clamps (copies the
-// nearest interior cell). Any integer i is accepted.
+// nearest interior cell), reflective mirrors (ghost -1-k is the image of
+// cell k, ghost n+k of cell n-1-k). Any integer i is accepted and the result
+// is always in [0, n): lanes further out than the mirror reaches (only the
+// two ghosts next to a wall enter the scheme) are clamped to an edge cell.
 HWENO_HD int map_index(int i, int n, int lo, int hi) {
   if (i >= 0 && i < n) return i;
   const int side = i < 0 ? lo : hi;
-  if (side == 0) {
+  if (side == kBcPeriodic) {
     int m = i % n;
     return m < 0 ? m + n : m;
   }
+  if (side == kBcReflective) {
+    const int m = i < 0 ? -1 - i : 2 * n - 1 - i;
+    return m < 0 ? 0 : (m > n - 1 ? n - 1 : m);
+  }
   return i < 0 ? 0 : n - 1;
+}
+
+// True for a ghost cell behind a reflective wall.
+HWENO_HD bool mirrored(int i, int n, int lo, int hi) {
+  return (i < 0 && lo == kBcReflective) || (i >= n && hi == kBcReflective);
+}
+
+// Sign rules of a reflective wall normal to direction D (remarks on boundary
+// conditions in sections 2 and 3, (RBC-1d), (RBC-2d-x), (RBC-2d-y)): the
+// ghost state is the mirror image with the normal momentum (component 1 + D)
+// negated; a derivative along the wall normal changes the sign of every other
+// component, a derivative along the wall behaves like the state. Only the
+// Euler systems have reflective walls.
+template <class Sys, int D, typename T>
+HWENO_HD void mirror_state(bool on, T (&U)[Sys::NC]) {
+  if constexpr (Sys::kChar) {
+    if (on) U[1 + D] = -U[1 + D];
+  }
+}
+template <class Sys, int D, typename T>
+HWENO_HD void mirror_normal_derivative(bool on, T (&A)[Sys::NC]) {
+  if constexpr (Sys::kChar) {
+    if (on) {
+#pragma unroll
+      for (int c = 0; c < Sys::NC; ++c)
+        if (c != 1 + D) A[c] = -A[c];
+    }
+  }
+}
+// Whether component c of field f is negated at a wall normal to D, for the
+// field order (u, derivative along x, derivative along y).
+HWENO_HD bool mirror_flips(int D, int f, int c) {
+  const bool normal = f == 1 + D;
+  return normal ? c != 1 + D : c == 1 + D;
 }
 
 }  // namespace hweno

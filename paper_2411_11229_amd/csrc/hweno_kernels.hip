@@ -165,6 +165,11 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
     U[c] = A.U[c * A.plane + g];
     V[c] = A.V[c * A.plane + g];
   }
+  {
+    const bool m = mirrored(col, A.nx, A.bc[0], A.bc[1]);
+    mirror_state<Sys, 0>(m, U);
+    mirror_normal_derivative<Sys, 0>(m, V);
+  }
   double RU[NC], RV[NC], RW[NC];
   T vt[NC];
   sweep_x<2>(sy, A.s, ax, U, V, W, RU, RV, RW, vt);
@@ -198,9 +203,15 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
 }
 
 // ------------------------------------------------------------ 2D stage kernel
-template <class Sys, typename T>
-__device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol,
-                                         T (&U)[Sys::NC], T (&V)[Sys::NC], T (&W)[Sys::NC]) {
+// Loads row r of column gcol (ghost rows and columns by index map). With
+// WALLS (some boundary is reflective): xm, this lane is a ghost column behind
+// a reflective wall; xwall, some lane of the wavefront is (wave-uniform, so
+// unaffected blocks skip the sign rules). Problems without walls use the
+// kernel without this code, whose register allocation it would disturb.
+template <class Sys, bool WALLS, typename T>
+__device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol, bool xwall,
+                                         bool xm, T (&U)[Sys::NC], T (&V)[Sys::NC],
+                                         T (&W)[Sys::NC]) {
   const int gr = map_index(r, A.ny, A.bc[2], A.bc[3]);
   const int off = gr * A.nx + gcol;
 #pragma unroll
@@ -209,9 +220,21 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol,
     V[c] = A.V[c * A.plane + off];
     W[c] = A.W[c * A.plane + off];
   }
+  if constexpr (Sys::kChar && WALLS) {
+    if (xwall) {
+      mirror_state<Sys, 0>(xm, U);
+      mirror_normal_derivative<Sys, 0>(xm, V);
+      mirror_state<Sys, 0>(xm, W);
+    }
+    if (mirrored(r, A.ny, A.bc[2], A.bc[3])) {
+      mirror_state<Sys, 1>(true, U);
+      mirror_state<Sys, 1>(true, V);
+      mirror_normal_derivative<Sys, 1>(true, W);
+    }
+  }
 }
 
-template <class Sys, typename T, int MODE>
+template <class Sys, typename T, int MODE, bool WALLS>
 __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   if (MODE != kRhs && A.active && *A.active == 0) return;
@@ -220,6 +243,10 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   const int col = blockIdx.x * kXOut - kHalo + lane;
   const int gcol = map_index(col, A.nx, A.bc[0], A.bc[1]);
   const bool out_col = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
+  const bool xm = mirrored(col, A.nx, A.bc[0], A.bc[1]);
+  const int col0 = blockIdx.x * kXOut - kHalo;   // the wavefront's first column
+  const bool xwall = (A.bc[0] == kBcReflective && col0 < 0) ||
+                     (A.bc[1] == kBcReflective && col0 + kWave > A.nx);
   const int y0 = blockIdx.y * A.rows;
   const int y1 = min(y0 + A.rows, A.ny);
   const double ax = A.alpha[0], ay = A.alpha[1];
@@ -243,12 +270,12 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   unsigned flag = 0;
 
   T Un[NC], Vn[NC], Wn[NC];
-  load_row<Sys>(A, y0 - 2, gcol, Un, Vn, Wn);
+  load_row<Sys, WALLS>(A, y0 - 2, gcol, xwall, xm, Un, Vn, Wn);
   for (int r = y0 - 2; r < y1 + 2; ++r) {
     T Uc[NC], Vc[NC], Wc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) { Uc[c] = Un[c]; Vc[c] = Vn[c]; Wc[c] = Wn[c]; }
-    if (r + 1 < y1 + 2) load_row<Sys>(A, r + 1, gcol, Un, Vn, Wn);  // prefetch
+    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, r + 1, gcol, xwall, xm, Un, Vn, Wn);  // prefetch
     // RK base of this iteration's output row, loaded early to hide latency
     T Bu[NC], Bv[NC], Bw[NC];
     if (MODE >= kStage2 && r >= y0 + 2 && out_col) {
@@ -514,6 +541,30 @@ __global__ void ws_init_kernel(StepScalars* sc) {
 // [-2, n+2) is an output lane of exactly one block; contributions to ghost
 // cells go to a side buffer and are folded into their images by
 // ghost_fold_kernel (the transpose of the ghost index map).
+// The ghost cells whose image is cell x of a line of n cells: slots 0..3 are
+// the virtual cells -2, -1, n, n+1; a cell is the image of at most two of
+// them (a transmissive edge cell of both ghosts of its side), listed in slot
+// order, each with whether the reflective sign rules apply.
+struct GhostImages {
+  int a, b;
+  bool flip_a, flip_b;
+};
+__device__ __forceinline__ GhostImages ghost_images(int x, int n, int lo, int hi) {
+  GhostImages g{-1, -1, false, false};
+  for (int k = 0; k < 4; ++k) {
+    const int v = k < 2 ? k - 2 : n + k - 2;
+    if (map_index(v, n, lo, hi) != x) continue;
+    if (g.a < 0) {
+      g.a = k;
+      g.flip_a = mirrored(v, n, lo, hi);
+    } else {
+      g.b = k;
+      g.flip_b = mirrored(v, n, lo, hi);
+    }
+  }
+  return g;
+}
+
 template <typename T>
 struct VjpArgs {
   const T* X[3];          // u, along-derivative, other derivative (null in 1D)
@@ -533,7 +584,7 @@ struct VjpArgs {
   Scheme s;
 };
 
-template <class Sys, typename T, int D, int NF, int NA>
+template <class Sys, typename T, int D, int NF, int NA, bool WALLS>
 __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   using Bar = typename BarOf<Sys, T>::type;
@@ -555,6 +606,12 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     U[c] = A.X[0][c * A.plane + base + g];
     Av[c] = A.X[1][c * A.plane + base + g];
     Ov[c] = NF == 3 ? A.X[2][c * A.plane + base + g] : T(0);
+  }
+  if constexpr (WALLS) {
+    const bool m = mirrored(v, A.n, A.bc_lo, A.bc_hi);
+    mirror_state<Sys, D>(m, U);
+    mirror_normal_derivative<Sys, D>(m, Av);
+    mirror_state<Sys, D>(m, Ov);
   }
   // cotangents; zero at ghost cells (L and B are defined on interior cells)
   T aU[NC], aA[NC], bU[NC], bA[NC], bO[NC];
@@ -715,11 +772,11 @@ struct VjpYArgs {
   const T* xghost;        // x-pass ghost columns [ny][4][3][NC], folded here
   int nx, ny, rows, plane;
   int bc_lo, bc_hi;
-  int x_periodic;
+  int bcx_lo, bcx_hi;     // boundaries of the x-pass, whose ghost columns are folded here
   Scheme s;
 };
 
-template <class Sys, typename T>
+template <class Sys, typename T, bool WALLS>
 __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   using Bar = typename BarOf<Sys, T>::type;
@@ -741,6 +798,8 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
   T accUa[NC], accWa[NC], accUb[NC], accWb[NC];      // HWENO-reverse sums of rows r-2, r-1
 #pragma unroll
   for (int c = 0; c < NC; ++c) { accUa[c] = T(0); accWa[c] = T(0); accUb[c] = T(0); accWb[c] = T(0); }
+  // wavefronts holding column 0, 1, nx-2 or nx-1 fold the x-pass ghost columns
+  const bool xedge = blockIdx.x == 0 || (blockIdx.x + 1) * kWave >= A.nx - 1;
   for (int r = o0 - 2; r < o1 + 2; ++r) {
     const int gr = map_index(r, A.ny, A.bc_lo, A.bc_hi);
     const bool inrow = r >= 0 && r < A.ny;
@@ -757,6 +816,13 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
         bVc[c] = cbt * A.b[1][idx];
         bWc[c] = cbt * A.b[2][idx];
         for (int k = 0; k < A.na; ++k) aWc[c] += T(A.ca[k]) * A.aw[k][idx];
+      }
+    }
+    if constexpr (WALLS) {
+      if (mirrored(r, A.ny, A.bc_lo, A.bc_hi)) {
+        mirror_state<Sys, 1>(true, Uc);
+        mirror_state<Sys, 1>(true, Vc);
+        mirror_normal_derivative<Sys, 1>(true, Wc);
       }
     }
     // interface (r-1)+1/2: L_j = -(F_{j+1/2} - F_{j-1/2}) / dy
@@ -854,25 +920,23 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
       prim_vjp(sy, Ua, q, bq, gU);
       if (colok) {
         if (o >= 0 && o < A.ny) {
-          // x-pass ghost columns of this row: their images are the edge columns
-          int sa = -1, sb = -1;
-          if (A.x_periodic) {
-            sa = x == A.nx - 2 ? 0 : x == A.nx - 1 ? 1 : x == 0 ? 2 : x == 1 ? 3 : -1;
-          } else if (x == 0) {
-            sa = 0; sb = 1;
-          } else if (x == A.nx - 1) {
-            sa = 2; sb = 3;
-          }
+          // x-pass ghost columns of this row folded into their images
+          GhostImages xs{-1, -1, false, false};
+          if (xedge) xs = ghost_images(x, A.nx, A.bcx_lo, A.bcx_hi);
           const T* xg = A.xghost + (size_t)o * 4 * 3 * NC;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const int idx = c * A.plane + o * A.nx + x;
             T gx[3] = {A.G[0][idx], A.G[1][idx], A.G[2][idx]};
-            if (sa >= 0) {
+            if (xs.a >= 0) {
 #pragma unroll
               for (int f = 0; f < 3; ++f) {
-                gx[f] += xg[sa * 3 * NC + f * NC + c];
-                if (sb >= 0) gx[f] += xg[sb * 3 * NC + f * NC + c];
+                const T ga = xg[xs.a * 3 * NC + f * NC + c];
+                gx[f] += WALLS && xs.flip_a && mirror_flips(0, f, c) ? -ga : ga;
+                if (xs.b >= 0) {
+                  const T gb = xg[xs.b * 3 * NC + f * NC + c];
+                  gx[f] += WALLS && xs.flip_b && mirror_flips(0, f, c) ? -gb : gb;
+                }
               }
             }
             A.G[0][idx] = gx[0] + gU[c];
@@ -924,15 +988,16 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
 // boundary and to no ghost image); threads (last slot, column, field,
 // component) handle, in a fixed order, the boundaries near the edges (halo
 // terms aimed at ghost rows go into the ghost side buffer) and then the ghost
-// rows: periodic rows -2, -1, ny, ny+1 map to ny-2, ny-1, 0, 1, transmissive
-// ones to 0, 0, ny-1, ny-1 (both sides share one boundary type). Strip k owns
-// the virtual rows [-2 + k R, -2 + (k+1) R).
+// rows -2, -1, ny, ny+1, each into its image by the boundary's index map
+// (periodic: ny-2, ny-1, 0, 1; transmissive: 0, 0, ny-1, ny-1; reflective:
+// 1, 0, ny-1, ny-2 with the wall's sign rules). Images are always edge rows.
+// Strip k owns the virtual rows [-2 + k R, -2 + (k+1) R).
 template <typename T>
 __global__ __launch_bounds__(256) void vjp_y_fold_kernel(T* __restrict__ G0, T* __restrict__ G1,
                                                          T* __restrict__ G2, T* __restrict__ ghost,
                                                          const T* __restrict__ halo, int nx, int ny,
                                                          int plane, int nc, int R, int nstrips,
-                                                         int periodic) {
+                                                         int lo, int hi) {
   const long per = 3L * nc * nx;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= per * nstrips) return;
@@ -981,29 +1046,23 @@ __global__ __launch_bounds__(256) void vjp_y_fold_kernel(T* __restrict__ G0, T* 
   }
   const size_t gs = (size_t)3 * nc * nx;
   const T* gp = ghost + (size_t)fc * nx + x;
-  const T g0 = gp[0], g1 = gp[gs], g2 = gp[2 * gs], g3 = gp[3 * gs];
-  if (periodic) {
-    const size_t r0 = (size_t)(ny - 2) * nx, r1 = (size_t)(ny - 1) * nx, r3 = (size_t)nx;
-    const T a0 = G[r0], a1 = G[r1], a2 = G[0], a3 = G[r3];
-    G[r0] = a0 + g0;
-    G[r1] = a1 + g1;
-    G[0] = a2 + g2;
-    G[r3] = a3 + g3;
-  } else {
-    const size_t rl = (size_t)(ny - 1) * nx;
-    const T a0 = G[0], a1 = G[rl];
-    G[0] = (a0 + g0) + g1;
-    G[rl] = (a1 + g2) + g3;
+  const T gv[4] = {gp[0], gp[gs], gp[2 * gs], gp[3 * gs]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {   // ghost rows -2, -1, ny, ny+1
+    const int v = k < 2 ? k - 2 : ny + k - 2;
+    const bool neg = mirrored(v, ny, lo, hi) && mirror_flips(1, f, c);
+    G[(size_t)map_index(v, ny, lo, hi) * nx] += neg ? -gv[k] : gv[k];
   }
 }
 
-// Adds the ghost-cell contributions to the cells they were copied from, in a
-// fixed order (one thread per line, field and component).
+// Adds the ghost-cell contributions to the cells they were copied from (with
+// the reflective sign rules where a wall mirrors them), in a fixed order (one
+// thread per line, field and component).
 template <typename T>
 __global__ __launch_bounds__(256) void ghost_fold_kernel(T* __restrict__ G0, T* __restrict__ G1,
                                                          T* __restrict__ G2,
                                                          const T* __restrict__ ghost, int n, int rows,
-                                                         int plane, int nc, int nf, int periodic) {
+                                                         int plane, int nc, int nf, int lo, int hi) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = rows * nf * nc;
   if (t >= total) return;
@@ -1013,17 +1072,12 @@ __global__ __launch_bounds__(256) void ghost_fold_kernel(T* __restrict__ G0, T* 
   T* G = (f == 0 ? G0 : (f == 1 ? G1 : G2)) + (size_t)c * plane + (size_t)row * n;
   const T* gp = ghost + (size_t)row * 4 * 3 * nc + f * nc + c;
   const int gs = 3 * nc;
-  const T g0 = gp[0], g1 = gp[gs], g2 = gp[2 * gs], g3 = gp[3 * gs];
-  if (periodic) {
-    const T a0 = G[n - 2], a1 = G[n - 1], a2 = G[0], a3 = G[1];
-    G[n - 2] = a0 + g0;
-    G[n - 1] = a1 + g1;
-    G[0] = a2 + g2;
-    G[1] = a3 + g3;
-  } else {
-    const T a0 = G[0], a1 = G[n - 1];
-    G[0] = (a0 + g0) + g1;
-    G[n - 1] = (a1 + g2) + g3;
+  const T gv[4] = {gp[0], gp[gs], gp[2 * gs], gp[3 * gs]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {   // virtual cells -2, -1, n, n+1
+    const int v = k < 2 ? k - 2 : n + k - 2;
+    const bool neg = mirrored(v, n, lo, hi) && mirror_flips(0, f, c);
+    G[map_index(v, n, lo, hi)] += neg ? -gv[k] : gv[k];
   }
 }
 
@@ -1062,8 +1116,13 @@ hweno_status validate(const hweno_problem* p) {
   if (!(p->gamma0 > 0.0 && p->gamma0 < 1.0)) return HWENO_EINVAL;
   if (!(p->d0 > 0.0 && p->d0 < 1.0)) return HWENO_EINVAL;
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return HWENO_EINVAL;
-  for (int k = 0; k < 4; ++k)
-    if (p->bc[k] != HWENO_PERIODIC && p->bc[k] != HWENO_TRANSMISSIVE) return HWENO_EINVAL;
+  for (int k = 0; k < 4; ++k) {
+    if (p->bc[k] != HWENO_PERIODIC && p->bc[k] != HWENO_TRANSMISSIVE &&
+        p->bc[k] != HWENO_REFLECTIVE)
+      return HWENO_EINVAL;
+    // reflective walls are defined for the Euler equations only
+    if (p->bc[k] == HWENO_REFLECTIVE && p->system != HWENO_EULER) return HWENO_EINVAL;
+  }
   if ((p->bc[0] == HWENO_PERIODIC) != (p->bc[1] == HWENO_PERIODIC)) return HWENO_EINVAL;
   if (p->dim == 2 && (p->bc[2] == HWENO_PERIODIC) != (p->bc[3] == HWENO_PERIODIC))
     return HWENO_EINVAL;
@@ -1254,11 +1313,25 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
       dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
       kernel<<<grid, kWave, 0, st>>>(A, sy);
     };
-    switch (mode) {
-      case kRhs: go(stage2d_kernel<Sys, T, kRhs>, std::integral_constant<int, kRhs>{}); break;
-      case kStage1: go(stage2d_kernel<Sys, T, kStage1>, std::integral_constant<int, kStage1>{}); break;
-      case kStage2: go(stage2d_kernel<Sys, T, kStage2>, std::integral_constant<int, kStage2>{}); break;
-      default: go(stage2d_kernel<Sys, T, kStage3>, std::integral_constant<int, kStage3>{}); break;
+    auto modes = [&](auto walls) {
+      constexpr bool W = decltype(walls)::value;
+      constexpr int kT = W ? 16 : 0;   // separate occupancy cache entries
+      switch (mode) {
+        case kRhs: go(stage2d_kernel<Sys, T, kRhs, W>, std::integral_constant<int, kRhs + kT>{}); break;
+        case kStage1: go(stage2d_kernel<Sys, T, kStage1, W>, std::integral_constant<int, kStage1 + kT>{}); break;
+        case kStage2: go(stage2d_kernel<Sys, T, kStage2, W>, std::integral_constant<int, kStage2 + kT>{}); break;
+        default: go(stage2d_kernel<Sys, T, kStage3, W>, std::integral_constant<int, kStage3 + kT>{}); break;
+      }
+    };
+    bool walls = false;
+    for (int k = 0; k < 4; ++k) walls = walls || A.bc[k] == kBcReflective;
+    if constexpr (Sys::kChar) {
+      if (walls)
+        modes(std::true_type{});
+      else
+        modes(std::false_type{});
+    } else {
+      modes(std::false_type{});
     }
   }
   return check_launch();
@@ -1337,16 +1410,28 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.ih = sc.idx;
     A.s = sc;
     dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
-    if (cot.na == 1)
-      vjp_row_kernel<Sys, T, 0, DIM + 1, 1><<<grid, kWave, 0, st>>>(A, sy);
-    else
-      vjp_row_kernel<Sys, T, 0, DIM + 1, 3><<<grid, kWave, 0, st>>>(A, sy);
+    const bool xwalls = p->bc[0] == HWENO_REFLECTIVE || p->bc[1] == HWENO_REFLECTIVE;
+    auto go = [&](auto walls) {
+      constexpr bool W = decltype(walls)::value;
+      if (cot.na == 1)
+        vjp_row_kernel<Sys, T, 0, DIM + 1, 1, W><<<grid, kWave, 0, st>>>(A, sy);
+      else
+        vjp_row_kernel<Sys, T, 0, DIM + 1, 3, W><<<grid, kWave, 0, st>>>(A, sy);
+    };
+    if constexpr (Sys::kChar) {
+      if (xwalls)
+        go(std::true_type{});
+      else
+        go(std::false_type{});
+    } else {
+      go(std::false_type{});
+    }
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     if constexpr (DIM == 1) {   // in 2D the y-pass folds these
       const int tot = ny * g.nf * NC;
       ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
                                                              nx, ny, plane, NC, g.nf,
-                                                             p->bc[0] == HWENO_PERIODIC);
+                                                             p->bc[0], p->bc[1]);
       if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     }
   }
@@ -1374,22 +1459,36 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.plane = plane;
     A.bc_lo = p->bc[2];
     A.bc_hi = p->bc[3];
-    A.x_periodic = p->bc[0] == HWENO_PERIODIC;
+    A.bcx_lo = p->bc[0];
+    A.bcx_hi = p->bc[1];
     A.s = sc;
     // strips of at least kMinStripRows rows (the halo buffer is sized for
     // that); warm-up: four rows of loads
-    int per_cu = 0, cus = 0;
-    const bool known = occupancy<4, kWave>(vjp_y_kernel<Sys, T>, &per_cu, &cus);
-    A.rows = balanced_rows((nx + kWave - 1) / kWave, ny + 4, known, per_cu, cus, 1.0, 16,
-                           kMinStripRows);
-    const int nstrips = (ny + 4 + A.rows - 1) / A.rows;
-    dim3 grid((nx + kWave - 1) / kWave, nstrips);
-    vjp_y_kernel<Sys, T><<<grid, kWave, 0, st>>>(A, sy);
+    bool walls = false;
+    for (int k = 0; k < 4; ++k) walls = walls || p->bc[k] == HWENO_REFLECTIVE;
+    int nstrips = 0;
+    auto go = [&](auto kernel, auto tag) {
+      int per_cu = 0, cus = 0;
+      const bool known = occupancy<decltype(tag)::value, kWave>(kernel, &per_cu, &cus);
+      A.rows = balanced_rows((nx + kWave - 1) / kWave, ny + 4, known, per_cu, cus, 1.0, 16,
+                             kMinStripRows);
+      nstrips = (ny + 4 + A.rows - 1) / A.rows;
+      dim3 grid((nx + kWave - 1) / kWave, nstrips);
+      kernel<<<grid, kWave, 0, st>>>(A, sy);
+    };
+    if constexpr (Sys::kChar) {
+      if (walls)
+        go(vjp_y_kernel<Sys, T, true>, std::integral_constant<int, 20>{});
+      else
+        go(vjp_y_kernel<Sys, T, false>, std::integral_constant<int, 4>{});
+    } else {
+      go(vjp_y_kernel<Sys, T, false>, std::integral_constant<int, 4>{});
+    }
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     const long tot = 3L * NC * nx * nstrips;
     vjp_y_fold_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
         out[0], out[1], out[2], (T*)wl.ghost_y, (const T*)wl.halo, nx, ny, plane, NC, A.rows, nstrips,
-        p->bc[2] == HWENO_PERIODIC);
+        p->bc[2], p->bc[3]);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
   }
   return HWENO_OK;

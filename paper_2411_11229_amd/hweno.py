@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, 'libhweno.so')
 
 SYSTEMS = {'advection': 0, 'burgers': 1, 'euler': 2}
-BCS = {'periodic': 0, 'transmissive': 1}
+BCS = {'periodic': 0, 'transmissive': 1, 'reflective': 2}
 PRECISIONS = {'f64': 0, 'f32': 1}
 DT_RULES = {'production': 0, 'accuracy': 1, 'fixed': 2}
 STATUS = {0: 'ok', -1: 'invalid argument', -2: 'unsupported', -3: 'HIP runtime error',

@@ -63,10 +63,21 @@ def test_workspace_size_valid_problem(lib):
     dict(d0=1.5), dict(eps=0.0), dict(bc=('periodic', 'transmissive', 'periodic', 'periodic')),
     dict(bc=('periodic', 'periodic', 'transmissive', 'periodic')),
     dict(nx=40000, ny=40000),
+    dict(system='burgers', bc=('reflective', 'reflective', 'periodic', 'periodic')),
+    dict(system='advection', bc=('periodic', 'periodic', 'transmissive', 'reflective')),
+    dict(bc=('reflective', 'periodic', 'periodic', 'periodic')),
 ])
 def test_invalid_problems_rejected(lib, bad):
     st, _ = _ws_bytes(lib, _prob(**bad))
     assert st == -1
+
+
+@pytest.mark.parametrize("bc", [('reflective',) * 4,
+                                ('reflective', 'transmissive', 'periodic', 'periodic'),
+                                ('transmissive', 'reflective', 'reflective', 'transmissive')])
+def test_reflective_walls_accepted_for_euler(lib, bc):
+    assert _ws_bytes(lib, _prob(bc=bc))[0] == 0
+    assert _ws_bytes(lib, _prob(dim=1, ny=1, bc=bc))[0] == 0
 
 
 def test_invalid_enum_values_rejected(lib):

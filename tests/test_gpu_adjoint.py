@@ -2,9 +2,10 @@
 
 * One step: <lambda, J delta> by Richardson-extrapolated central differences
   of the frozen-alpha step (hweno_step_frozen) against <J^T lambda, delta>
-  from hweno_adjoint_step, per system, both boundary types (relative 1e-6).
-  The differences use steps of 1e-7: the nonlinear weights make the map
-  strongly curved, and (4 D(e) - D(2e)) / 3 removes the e^2 term.
+  from hweno_adjoint_step, per system and boundary type (relative 1e-6).
+  The differences use steps of 1e-7 (1e-8 where FD_STEP says): the nonlinear
+  weights make the map strongly curved, and (4 D(e) - D(2e)) / 3 removes the
+  e^2 term.
 * Rollout: the gradient of J = dx dy/2 sum (U_T - U*)^2 w.r.t. (U0, V0, W0)
   against the FP64 oracle's reverse-mode gradient (torch-CPU, same source as
   the NumPy oracle, with its own recorded alphas and time steps), element by
@@ -52,7 +53,16 @@ def cases():
            ('euler1d-smooth', lambda: WL.random_smooth_1d(64, 'euler', seed=53)),
            ('burgers2d', lambda: WL.paper_burgers2d(40)),
            ('euler2d-smooth', lambda: WL.euler2d_smooth(70, seed=3101, ny=36)),
-           ('euler2d-quadrants', lambda: WL.euler2d_quadrants(48, seed=4101, ny=66))]
+           ('euler2d-quadrants', lambda: WL.euler2d_quadrants(48, seed=4101, ny=66)),
+           ('euler1d-reflective', lambda: WL.random_smooth_1d(61, 'euler', seed=54, bc='reflective')),
+           ('euler1d-reflective-transmissive',
+            lambda: WL.with_bc(WL.euler1d_riemann_sine(121, seed=2007),
+                               ('reflective', 'transmissive', 'periodic', 'periodic'))),
+           ('euler2d-reflective', lambda: WL.with_bc(WL.euler2d_smooth(61, seed=3103, ny=37),
+                                                     ('reflective',) * 4)),
+           ('euler2d-mixed-walls', lambda: WL.with_bc(WL.euler2d_quadrants(121, seed=4103, ny=23),
+                                                      ('transmissive', 'reflective',
+                                                       'reflective', 'transmissive')))]
 
     def adv2d():
         w = WL.paper_burgers2d(33)
@@ -61,6 +71,13 @@ def cases():
         return w
     out.append(('advection2d', adv2d))
     return out
+
+
+# Cases whose map is curved enough that the extrapolated differences need a
+# smaller step (walls next to piecewise-constant data: the oracle's own
+# reverse-mode gradient and its differences differ by 1.7e-5 at 1e-7 there,
+# by 6e-8 at 1e-8).
+FD_STEP = {'euler2d-mixed-walls': 1e-8}
 
 
 def state(w, dtype=torch.float64):
@@ -117,7 +134,7 @@ def test_adjoint_step_matches_finite_differences(name, mk):
         Xp = frozen_map(s, [x + e * d for x, d in zip(X, delta)], dt, rec)
         Xm = frozen_map(s, [x - e * d for x, d in zip(X, delta)], dt, rec)
         return sum(float((l * (p - m)).sum()) for l, p, m in zip(lam, Xp, Xm)) / (2 * e)
-    e = 1e-7
+    e = FD_STEP.get(name, 1e-7)
     fd = (4 * D(e) - D(2 * e)) / 3
     print(f'  adjoint {adj:.12e}  fd {fd:.12e}')
     assert adj == pytest.approx(fd, rel=1e-6, abs=1e-9 * sum(float(l.abs().sum()) for l in lam))
@@ -149,7 +166,14 @@ def _gpu_grad(w, steps, target, precision='f64', every=4):
 ROLL = [('euler2d-smooth', lambda: WL.euler2d_smooth(24, seed=3102, ny=20), 6),
         ('euler1d-riemann', lambda: WL.euler1d_riemann_sine(64, seed=2006), 9),
         ('burgers2d', lambda: WL.paper_burgers2d(20), 5),
-        ('euler2d-quadrants', lambda: WL.euler2d_quadrants(20, seed=4102, ny=18), 5)]
+        ('euler2d-quadrants', lambda: WL.euler2d_quadrants(20, seed=4102, ny=18), 5),
+        ('euler1d-reflective', lambda: WL.with_bc(WL.euler1d_riemann_sine(64, seed=2008),
+                                                  ('reflective', 'reflective', 'periodic', 'periodic')), 9),
+        ('euler2d-reflective', lambda: WL.with_bc(WL.euler2d_smooth(22, seed=3104, ny=19),
+                                                  ('reflective', 'transmissive', 'reflective', 'reflective')), 5),
+        ('euler2d-mixed-walls', lambda: WL.with_bc(WL.euler2d_quadrants(21, seed=4104, ny=18),
+                                                   ('transmissive', 'reflective', 'reflective',
+                                                    'transmissive')), 4)]
 
 
 @pytest.mark.parametrize("name,mk,steps", ROLL, ids=[c[0] for c in ROLL])
