@@ -206,3 +206,60 @@ def test_reflective_rejected_for_scalar_laws():
     w = WL.random_smooth_1d(12, 'burgers', seed=3, bc='reflective')
     with pytest.raises(hweno.HwenoError):
         solver(w)
+
+
+def _blast_final_gpu(gamma0, d0, n=800):
+    w = WL.blast_wave_1d(n)
+    s = solver(w, gamma0=gamma0, d0=d0)
+    U, V = dev(w.U), dev(w.V)
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    k = 0
+    while True:
+        for _ in range(64):
+            s.step(U, V, None, t, w.t_end, cfl=0.1 if k == 0 else 0.6)
+            k += 1
+        if float(t.item()) >= w.t_end:
+            break
+    s.health()
+    return w.x, host(U)
+
+
+G0_SWEEP = (0.95, 0.7, 0.5, 1.0 / 3.0, 0.1)
+D0_SWEEP = (0.95, 0.9, 0.7, 0.5, 1.0 / 3.0, 0.1)
+
+
+def test_blast_wave_linear_weight_sweeps_on_gpu():
+    """The paper's sweeps of Example 4.4 at N = 800: gamma0 over
+    (0.95, 0.7, 0.5, 1/3, 0.1) with d0 = 0.9 lowers the density peak in
+    (0.7, 0.8) step by step; d0 over (0.95, ..., 0.1) with gamma0 = 0.95 raises
+    the total variation of the density step by step."""
+    peak = []
+    for g0 in G0_SWEEP:
+        x, U = _blast_final_gpu(g0, 0.9)
+        peak.append(U[0][(x > 0.7) & (x < 0.8)].max())
+    tv = []
+    for d0 in D0_SWEEP:
+        x, U = _blast_final_gpu(0.95, d0)
+        tv.append(np.abs(np.diff(U[0])).sum())
+    print('peaks', peak, 'TV', tv)
+    assert all(a > b for a, b in zip(peak, peak[1:])), peak
+    assert all(a < b for a, b in zip(tv, tv[1:])), tv
+
+
+@pytest.mark.parametrize("g0,d0", [(1.0 / 3.0, 0.9), (0.95, 0.1)])
+def test_blast_wave_sweep_settings_match_oracle(g0, d0):
+    """Parity with the oracle over the first 120 steps at swept weights."""
+    w = WL.blast_wave_1d(800)
+    s = solver(w, gamma0=g0, d0=d0)
+    U, V = dev(w.U), dev(w.V)
+    _blast_steps(s, U, V, w.t_end, n_steps=120)
+    p = oprob(w, gamma0=g0, d0=d0)
+
+    def run(a, b, c):
+        for k in range(120):
+            al = O.max_speed(p, a)
+            dt = O.time_step(p, al, 'production', 0.1 if k == 0 else 0.6)
+            a, b, _, _ = O.step(p, a, b, None, dt, (al, None, None))
+        return a, b
+    base, worst = oracle_sensitivity(p, w, run)
+    check_run(w, (U, V), base, worst, f'blast-g0={g0:.3f}-d0={d0:.3f}')

@@ -13,7 +13,8 @@
   vanish at a reflective wall and total mass and energy are invariant.
 * Example 4.4 (Woodward-Colella blast waves, N = 800, t = 0.038): the
   density range over the space-time plane printed with the paper's contour
-  plot, 0.1470 to 23.2289.
+  plot, 0.1470 to 23.2289; and the trends the paper reports for its sweeps of
+  the linear weights gamma0 and d0.
 """
 import json
 import os
@@ -161,3 +162,34 @@ def test_blast_wave_density_range_matches_paper():
     assert abs(hi - ref['max']) <= 2e-3 * ref['max']
     # mass is conserved between the walls (initial mass 1)
     assert abs(U[0].sum() * (1.0 / 800) - 1.0) <= 1e-12
+
+
+def _blast_final(n, gamma0, d0):
+    w = WL.blast_wave_1d(n)
+    p = O.Problem(**w.problem_kwargs(), gamma0=gamma0, d0=d0)
+    U, V, t, k = w.U, w.V, 0.0, 0
+    while t < w.t_end:
+        alpha = O.max_speed(p, U)
+        dt = O.time_step(p, alpha, 'production', 0.1 if k == 0 else 0.6)
+        if t + dt >= w.t_end:
+            dt = w.t_end - t
+        U, V, _, _ = O.step(p, U, V, None, dt, (alpha, None, None))
+        t, k = t + dt, k + 1
+    return w.x, U
+
+
+def test_blast_wave_linear_weight_sweeps_follow_paper():
+    """Example 4.4's sweeps of the linear weights (N = 400 here): a smaller
+    gamma0 lowers the resolution (the density peak in (0.7, 0.8) drops), a
+    smaller d0 sharpens the profile and lets oscillations in (the total
+    variation of the density grows)."""
+    peak, tv = {}, {}
+    for g0, d0 in ((0.95, 0.9), (0.5, 0.9), (0.1, 0.9), (0.95, 0.5), (0.95, 0.1)):
+        x, U = _blast_final(400, g0, d0)
+        assert np.isfinite(U).all()
+        r = U[0]
+        peak[g0, d0] = r[(x > 0.7) & (x < 0.8)].max()
+        tv[g0, d0] = np.abs(np.diff(r)).sum()
+    print(peak, tv)
+    assert peak[0.95, 0.9] > peak[0.5, 0.9] > peak[0.1, 0.9]
+    assert tv[0.95, 0.9] < tv[0.95, 0.5] < tv[0.95, 0.1]
