@@ -32,6 +32,9 @@ notes of the repository):
     and L = R^{-1}. D(f), D(h), LF and the mixed fluxes act component-wise.
   * Transmissive boundary: zero-order extrapolation of U, V and W into the two
     ghost cells.
+  * Characteristic basis switch ('interface'): u^-_{i+1/2} and u^+_{i+1/2}
+    in the eigenvectors of Roe's average of U_i, U_{i+1} (Jiang and Shu);
+    v~ keeps the cell basis.
   * Reflective boundary (Euler only): mirror cells with the sign rules of
     (RBC-1d), (RBC-2d-x), (RBC-2d-y); ghost -1-k is the image of cell k.
 """
@@ -66,6 +69,7 @@ class Problem:
     d0: float = 0.9
     eps: float = 1e-10
     bc: tuple = ('periodic', 'periodic', 'periodic', 'periodic')  # x_lo x_hi y_lo y_hi
+    basis: str = 'cell'             # characteristic basis: 'cell' | 'interface'
 
     def __post_init__(self):
         if self.gamma0 is None:
@@ -221,6 +225,31 @@ class Euler:
         rho, mu, nu, P, c, H = self.primitives(U)
         vel = mu if d == 0 else nu
         return xp.amax(abs(vel) + c)
+
+
+def roe_state(sys, UL, UR):
+    """A state whose flux Jacobian is Roe's average matrix of UL and UR (the
+    interface basis of Jiang and Shu's characteristic decomposition, cited by
+    the remark on systems in section 2): the sqrt(rho)-weighted averages of the
+    velocities and of the total enthalpy H, the density sqrt(rho_L rho_R), and
+    the pressure that gives the averaged sound speed
+    c^2 = (gamma-1)(H - |vel|^2/2). The Jacobian depends on the velocities and
+    H only, so its eigenvectors are Roe's."""
+    rl, ul, vl, _, _, hl = sys.primitives(UL)
+    rr, ur, vr, _, _, hr = sys.primitives(UR)
+    xp = _array.ns(UL)
+    wl, wr = xp.sqrt(rl), xp.sqrt(rr)
+    u = (wl * ul + wr * ur) / (wl + wr)
+    v = (wl * vl + wr * vr) / (wl + wr)
+    H = (wl * hl + wr * hr) / (wl + wr)
+    rho = wl * wr
+    k = 0.5 * (u * u + v * v)
+    c2 = (sys.g - 1.0) * (H - k)
+    P = rho * c2 / sys.g
+    E = P / (sys.g - 1.0) + rho * k
+    if sys.dim == 1:
+        return xp.stack([rho, rho * u, E])
+    return xp.stack([rho, rho * u, rho * v, E])
 
 
 def make_system(prob):
@@ -409,7 +438,7 @@ def lax_friedrichs(fm, fp, um, up, alpha):
 # ----------------------------------------------------------------------------
 # One directional sweep: Steps 1-3 of section 2 (and Steps 1/2 of section 3)
 # ----------------------------------------------------------------------------
-def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps):
+def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis='cell'):
     """HWENO-I procedure along the last axis for direction ``d``.
 
     U: state; A: derivative along the sweep (v for x, w for y); B: the other
@@ -437,6 +466,19 @@ def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps):
     uR, uL, _, _, vt = hweno_cell(wm, w0, wp, am, ap, h, lin_gamma, lin_d, eps)
     if eig is not None:
         uR, uL, vt = xp.matvec(Rc, uR), xp.matvec(Rc, uL), xp.matvec(Rc, vt)
+    if eig is not None and basis == 'interface':
+        # Jiang-Shu: the face values of cell j in the basis of that face (Roe
+        # average of the two cells sharing it); v~ stays in the cell basis.
+        # Interfaces between padded cells m and m+1, m = 0..n+2.
+        Lh, Rh = sys.eig(roe_state(sys, Up[..., :-1], Up[..., 1:]), d)
+        def in_basis(Lb):
+            pr = lambda X: xp.matvec(Lb, X)
+            return hweno_cell(pr(Um), pr(U0), pr(Upl), pr(Am), pr(Apl), h, lin_gamma, lin_d, eps)
+        uR = xp.matvec(Rh[..., 1:n + 3, :, :], in_basis(Lh[..., 1:n + 3, :, :])[0])
+        uL = xp.matvec(Rh[..., 0:n + 2, :, :], in_basis(Lh[..., 0:n + 2, :, :])[1])
+    elif basis != 'cell':
+        if eig is not None:
+            raise ValueError(basis)
     # v^{+-} = p0'(faces): linear in the data, so taken component-wise
     _, _, vR, vL, _ = hweno_cell(Um, U0, Upl, Am, Apl, h, lin_gamma, lin_d, eps)
     # interface k+1/2 for k=-1..n-1: minus side from cell k, plus side from k+1
@@ -480,17 +522,17 @@ def rhs(prob, U, V, W=None, alpha=None):
     sys = make_system(prob)
     if alpha is None:
         alpha = max_speed(prob, U)
-    g, dl, eps = prob.linear_gamma, prob.linear_d, prob.eps
+    g, dl, eps, bs = prob.linear_gamma, prob.linear_d, prob.eps, prob.basis
     bx0, bx1, by0, by1 = prob.bc
     if prob.dim == 1:
-        L1, L2, _, vt = sweep(sys, 0, U, V, None, prob.dx, alpha[0], bx0, bx1, g, dl, eps)
+        L1, L2, _, vt = sweep(sys, 0, U, V, None, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs)
         return L1, L2, None, vt, None
     xp = _array.ns(U)
     # Step 1: x-direction on (u, v); mixed flux eta = f'(u) w
-    Lx1, Lx2, Lx3, vt = sweep(sys, 0, U, V, W, prob.dx, alpha[0], bx0, bx1, g, dl, eps)
+    Lx1, Lx2, Lx3, vt = sweep(sys, 0, U, V, W, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs)
     # Step 2: y-direction on (u, w); mixed flux xi = g'(u) v
     t = lambda a: xp.moveaxis(a, -1, -2)
-    Ly1, Ly3, Ly2, wt = sweep(sys, 1, t(U), t(W), t(V), prob.dy, alpha[1], by0, by1, g, dl, eps)
+    Ly1, Ly3, Ly2, wt = sweep(sys, 1, t(U), t(W), t(V), prob.dy, alpha[1], by0, by1, g, dl, eps, bs)
     # Step 4
     return Lx1 + t(Ly1), Lx2 + t(Ly2), Lx3 + t(Ly3), vt, t(wt)
 

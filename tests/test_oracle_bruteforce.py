@@ -6,7 +6,10 @@ from ``numpy.linalg.eig`` rescaled to the stated normalisation. It reuses only
 the oracle's scalar formula functions (which the coefficient pins check), so
 it tests the array plumbing of the oracle: padding, slicing offsets, the
 characteristic projections, the axis handling of the y-sweep and the residual
-assembly of (odeH)/(ode2H).
+assembly of (odeH)/(ode2H). For the interface basis it takes the Roe state
+from the oracle's ``roe_state`` (pinned by Roe's property below: a pair alone
+does not determine the matrix when the jump is a pure density change, so the
+property cannot stand in for the formula here) and its own eigenvectors.
 """
 import cmath
 
@@ -75,6 +78,11 @@ def bf_eigvecs(u, d):
     return R
 
 
+def bf_roe_state(ul, ur):
+    sy = O.Euler(G, len(ul) - 2)
+    return list(O.roe_state(sy, np.array(ul, dtype=float)[:, None], np.array(ur, dtype=float)[:, None])[:, 0])
+
+
 def mapidx(i, n, lo, hi):
     if 0 <= i < n:
         return i
@@ -82,7 +90,7 @@ def mapidx(i, n, lo, hi):
     return i % n if side == 'periodic' else min(max(i, 0), n - 1)
 
 
-def bf_line(sysname, d, Uc, Ac, Bc, n, h, alpha, bc, lg, ld, eps, adv):
+def bf_line(sysname, d, Uc, Ac, Bc, n, h, alpha, bc, lg, ld, eps, adv, basis='cell'):
     """One grid line. Uc(i)/Ac(i)/Bc(i) return the component lists at cell i
     (any integer; ghost mapping applied here)."""
     get = lambda F, i: F(mapidx(i, n, bc[0], bc[1]))
@@ -105,6 +113,18 @@ def bf_line(sysname, d, Uc, Ac, Bc, n, h, alpha, bc, lg, ld, eps, adv):
             r_, l_, _, _, t_ = O.hweno_cell(wm[k], w0[k], wp[k], qm[k], qp[k], h, lg, ld, eps)
             cr.append(r_), cl.append(l_), ct.append(t_)
         uR[i], uL[i], vt[i] = list(R @ cr), list(R @ cl), list(R @ ct)
+        if sysname == 'euler' and basis == 'interface':
+            for side, (a, b) in (('R', (u0, up)), ('L', (um, u0))):
+                Rf = bf_eigvecs(bf_roe_state(a, b), d)
+                Lf = np.linalg.inv(Rf)
+                pr = lambda v: list(Lf @ np.array(v))
+                wm, w0, wp, qm, qp = pr(um), pr(u0), pr(up), pr(am), pr(ap)
+                c = [O.hweno_cell(wm[k], w0[k], wp[k], qm[k], qp[k], h, lg, ld, eps)[0 if side == 'R' else 1]
+                     for k in range(nc)]
+                if side == 'R':
+                    uR[i] = list(Rf @ c)
+                else:
+                    uL[i] = list(Rf @ c)
         vR[i], vL[i] = [], []
         for k in range(nc):
             _, _, a_, b_, _ = O.hweno_cell(um[k], u0[k], up[k], am[k], ap[k], h, lg, ld, eps)
@@ -135,13 +155,13 @@ def bf_line(sysname, d, Uc, Ac, Bc, n, h, alpha, bc, lg, ld, eps, adv):
     return RU, RA, RB, [vt[i] for i in range(n)]
 
 
-def bf_rhs(w, alpha, lg, ld, eps=1e-10):
+def bf_rhs(w, alpha, lg, ld, eps=1e-10, basis='cell'):
     nc = w.U.shape[0]
     adv = (w.adv_a, w.adv_b)
     if w.dim == 1:
         col = lambda F: (lambda i: [F[c, i] for c in range(nc)])
         RU, RA, _, vt = bf_line(w.system, 0, col(w.U), col(w.V), None, w.nx, w.dx, alpha[0],
-                                w.bc[0:2], lg, ld, eps, adv)
+                                w.bc[0:2], lg, ld, eps, adv, basis)
         T = lambda L: np.array(L).T
         return T(RU), T(RA), None, T(vt), None
     ny, nx = w.ny, w.nx
@@ -150,7 +170,7 @@ def bf_rhs(w, alpha, lg, ld, eps=1e-10):
     for j in range(ny):
         row = lambda F: (lambda i: [F[c, j, i] for c in range(nc)])
         RU, RA, RB, t = bf_line(w.system, 0, row(w.U), row(w.V), row(w.W), nx, w.dx, alpha[0],
-                                w.bc[0:2], lg, ld, eps, adv)
+                                w.bc[0:2], lg, ld, eps, adv, basis)
         L1[:, j, :] += np.array(RU).T
         L2[:, j, :] += np.array(RA).T
         L3[:, j, :] += np.array(RB).T
@@ -158,7 +178,7 @@ def bf_rhs(w, alpha, lg, ld, eps=1e-10):
     for i in range(nx):
         colf = lambda F: (lambda k: [F[c, k, i] for c in range(nc)])
         RU, RA, RB, t = bf_line(w.system, 1, colf(w.U), colf(w.W), colf(w.V), ny, w.dy, alpha[1],
-                                w.bc[2:4], lg, ld, eps, adv)
+                                w.bc[2:4], lg, ld, eps, adv, basis)
         L1[:, :, i] += np.array(RU).T
         L3[:, :, i] += np.array(RA).T
         L2[:, :, i] += np.array(RB).T
@@ -199,3 +219,43 @@ def test_vectorised_oracle_matches_brute_force(name, w):
             continue
         scale = max(1.0, np.max(np.abs(b)))
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("name,w", [c for c in _cases() if 'euler' in c[0]],
+                         ids=[c[0] for c in _cases() if 'euler' in c[0]])
+def test_interface_basis_matches_brute_force(name, w):
+    """The interface-basis switch: face values in the eigenvectors of Roe's
+    matrix of the two cells sharing the face, v~ in the cell basis."""
+    prob = O.Problem(**w.problem_kwargs(), basis='interface')
+    alpha = O.max_speed(prob, w.U)
+    ref = bf_rhs(w, alpha, prob.linear_gamma, prob.linear_d, basis='interface')
+    got = O.rhs(prob, w.U, w.V, w.W, alpha)
+    cell = O.rhs(O.Problem(**w.problem_kwargs()), w.U, w.V, w.W, alpha)
+    differs = False
+    for a, b, c in zip(got, ref, cell):
+        if a is None:
+            continue
+        scale = max(1.0, np.max(np.abs(b)))
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * scale)
+        differs = differs or np.max(np.abs(a - c)) > 1e-9 * scale
+    assert differs   # the switch changes the result
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_roe_state_has_roes_property(dim):
+    """A(U~) (U_R - U_L) = F(U_R) - F(U_L) in every direction, for random
+    pairs of states (complex-step Jacobian of this file's own fluxes)."""
+    rng = np.random.default_rng(17 + dim)
+    for _ in range(20):
+        pair = []
+        for _ in range(2):
+            r, p = rng.uniform(0.1, 5.0), rng.uniform(0.1, 10.0)
+            vel = list(rng.uniform(-2.0, 2.0, dim))
+            k = 0.5 * sum(v * v for v in vel)
+            pair.append([r] + [r * v for v in vel] + [p / (G - 1.0) + r * k])
+        ul, ur = pair
+        roe = bf_roe_state(ul, ur)
+        for d in range(dim):
+            lhs = bf_jac('euler', roe, d, None) @ (np.array(ur) - np.array(ul))
+            rhs = np.array(bf_flux('euler', ur, d)) - np.array(bf_flux('euler', ul, d))
+            np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12 * np.max(np.abs(rhs)))

@@ -47,8 +47,8 @@ def burgers2d_exact(X, Y, t):
     return u
 
 
-def _run(w, gamma0):
-    prob = O.Problem(**w.problem_kwargs(), gamma0=gamma0)
+def _run(w, gamma0, basis='cell'):
+    prob = O.Problem(**w.problem_kwargs(), gamma0=gamma0, basis=basis)
     U, V, W, log = O.run(prob, w.U, w.V, w.W, w.t_end, rule='accuracy')
     return U
 
@@ -103,3 +103,17 @@ def test_mach2000_production_time_step():
     prob = O.Problem(**w.problem_kwargs())
     dt = O.time_step(prob, O.max_speed(prob, w.U), 'production', 0.6)
     assert dt == pytest.approx(GOLD['mach2000_dt']['value'], rel=2e-5)
+
+
+@pytest.mark.parametrize("table,mk,n", [('table2_euler1d', WL.paper_euler1d, 20),
+                                        ('table2_euler1d', WL.paper_euler1d, 40),
+                                        ('table4_euler2d', WL.paper_euler2d, 10)])
+def test_interface_basis_reproduces_euler_tables(table, mk, n):
+    """The Jiang-Shu interface basis (the other reading of the remark on
+    systems) gives the same printed digits on the smooth Euler tests."""
+    w = mk(n)
+    U = _run(w, GOLD[table]['gamma0'], basis='interface')
+    e = np.abs(U[0] - w.U[0])
+    _, l1, linf = _row(table, n)
+    assert e.max() == pytest.approx(linf, rel=REL)
+    assert e.mean() == pytest.approx(l1, rel=REL)
