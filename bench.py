@@ -77,11 +77,11 @@ class HipEvents:
             self.hip.hipEventDestroy(self.ev[i])
 
 
-def time_forward(n, precision, steps, warmup, seed=4000):
+def time_forward(n, precision, steps, warmup, seed=4000, basis='cell'):
     import torch
     from paper_2411_11229_amd import hweno, workloads
     w = workloads.euler2d_quadrants(n, seed=seed)
-    prob = hweno.Problem(**w.problem_kwargs(), precision=precision)
+    prob = hweno.Problem(**w.problem_kwargs(), precision=precision, basis=basis)
     s = hweno.Solver(prob)
     dt_ = prob.dtype
     U = torch.tensor(w.U, dtype=dt_, device='cuda')
@@ -201,6 +201,67 @@ def copy_probe(gib=1.0, reps=10):
                       'bytes_written_per_dispatch': n * 8, 'reps': reps}))
 
 
+def _run_until(s, U, V, W, t_end, max_steps):
+    """Steps to t_end in chunks; stops at the first chunk after which the
+    state flags report a non-finite or non-physical state (or t is not
+    finite). Returns (steps, t, status)."""
+    import torch
+    from paper_2411_11229_amd import hweno
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    k = 0
+    while k < max_steps:
+        for _ in range(32):
+            s.step(U, V, W, t, t_end)
+        k += 32
+        try:
+            s.health()
+        except hweno.HwenoError as e:
+            return k, float(t.item()), STATUS_NAMES.get(e.code, str(e.code))
+        tv = float(t.item())
+        if not tv == tv:
+            return k, tv, 'non-finite time'
+        if tv >= t_end:
+            break
+    return k, float(t.item()), 'ok' if float(t.item()) >= t_end else 'step limit'
+
+
+STATUS_NAMES = {-4: 'non-finite state', -5: 'non-physical state'}
+
+
+def basis_robustness():
+    """Cell vs interface characteristic basis on the 1D Riemann + sine data
+    (N = 2000, seeds 2000-2007, to each seed's T) and the 2D four-quadrant
+    data (256^2, seeds 4000-4007, to T = 0.25), FP64: whether each run
+    reaches T; and the 2048^2 stage-kernel time of both bases."""
+    import torch
+    from paper_2411_11229_amd import hweno, workloads
+    out = {'c2_euler1d_riemann_2000': {}, 'c4_euler2d_quadrants_256': {}}
+    for key, mk, seeds in (('c2_euler1d_riemann_2000', lambda sd: workloads.euler1d_riemann_sine(2000, seed=sd),
+                            range(2000, 2008)),
+                           ('c4_euler2d_quadrants_256', lambda sd: workloads.euler2d_quadrants(256, seed=sd),
+                            range(4000, 4008))):
+        for sd in seeds:
+            w = mk(sd)
+            row = {}
+            for basis in ('cell', 'interface'):
+                s = hweno.Solver(hweno.Problem(**w.problem_kwargs(), basis=basis))
+                d = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device='cuda')
+                U, V, W = d(w.U), d(w.V), d(w.W)
+                t0 = time.perf_counter()
+                k, t, st = _run_until(s, U, V, W, w.t_end, 200000)
+                torch.cuda.synchronize()
+                row[basis] = dict(status=st, t=t, steps_le=k, s=round(time.perf_counter() - t0, 3))
+            row['t_end'] = w.t_end
+            out[key][str(sd)] = row
+            print(json.dumps({key: {str(sd): row}}), file=sys.stderr, flush=True)
+    cost = {}
+    for basis in ('cell', 'interface'):
+        r = time_forward(2048, 'f64', 5, 2, basis=basis)
+        cost[basis] = r['avg_stage_ms']
+    out['stage_ms_2048_f64'] = cost
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument('--gpus', type=int, default=1)
@@ -213,6 +274,8 @@ def main():
     ap.add_argument('--adjoint-only', action='store_true',
                     help='time only the adjoint workload (for profiling)')
     ap.add_argument('--probe', choices=['copy'], help='run a calibration probe instead')
+    ap.add_argument('--basis-robustness', action='store_true',
+                    help='compare the cell and interface characteristic bases instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
                     help='precision of the headline run')
     args = ap.parse_args()
@@ -231,6 +294,9 @@ def main():
         sys.exit(1)
     if args.adjoint_only:
         print(json.dumps({'adjoint_f64': time_adjoint(args.precision)}))
+        return
+    if args.basis_robustness:
+        print(json.dumps({'basis_robustness': basis_robustness()}))
         return
 
     main_run = time_forward(args.n, args.precision, args.steps, args.warmup)

@@ -68,6 +68,16 @@ typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_s
  * The two ends of an axis are independent except for periodic. */
 typedef enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2 } hweno_bc;
 typedef enum { HWENO_F64 = 0, HWENO_F32 = 1 } hweno_precision;
+/* Characteristic basis of the HWENO interpolation for the Euler systems
+ * (remark on systems in section 2, local characteristic decomposition):
+ *   cell       the eigenvectors of A(U_i) serve both faces and the modified
+ *              derivative of cell i: one interpolation per cell and direction
+ *              (the reading the paper's efficiency argument needs);
+ *   interface  Jiang and Shu's form: u^-_{i+1/2}, u^+_{i+1/2} in the
+ *              eigenvectors of Roe's matrix of U_i and U_{i+1}, the modified
+ *              derivative in the cell basis (three interpolations per cell).
+ * Ignored for the scalar laws. The adjoint supports the cell basis only. */
+typedef enum { HWENO_BASIS_CELL = 0, HWENO_BASIS_INTERFACE = 1 } hweno_char_basis;
 typedef enum {
   HWENO_DT_PRODUCTION = 0,   /* dt = cfl / (ax/dx + ay/dy)                    */
   HWENO_DT_ACCURACY = 1,     /* dt = cfl / (ax/dx^(5/3) + ay/dy^(5/3))        */
@@ -95,6 +105,7 @@ typedef struct {
   double eps;           /* > 0                                                    */
   int32_t bc[4];        /* hweno_bc at x_lo, x_hi, y_lo, y_hi (see hweno_bc)      */
   int32_t precision;    /* hweno_precision of every array argument                */
+  int32_t char_basis;   /* hweno_char_basis                                       */
 } hweno_problem;
 
 /* Human-readable name of a status code (static string). */
@@ -189,7 +200,8 @@ hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void
  * (in the workspace, which also holds lambda2 and lambda1). At the kinks of
  * |beta0 - beta_k| the derivative of |.| is taken as sign(0) = 0. Output
  * buffers must not alias any input. The result is deterministic: every sum
- * is formed in a fixed order, without atomics.
+ * is formed in a fixed order, without atomics. Returns HWENO_EUNSUPPORTED
+ * for the Euler systems with the interface basis.
  */
 hweno_status hweno_adjoint_step(const hweno_problem* prob, const void* u_n, const void* v_n,
                                 const void* w_n, const void* stages, const double* dt,

@@ -373,6 +373,32 @@ struct Euler {
     e.b2 = e.b1 * q.k;
     return e;
   }
+  // The same basis for Roe's matrix of the states UL, UR (the interface basis
+  // of Jiang and Shu's characteristic decomposition): velocities and total
+  // enthalpy averaged with weights sqrt(rho), c^2 = (gas-1)(H - |vel|^2/2).
+  // With r = 1/sqrt(rho): sqrt(rho) u = m r and sqrt(rho) H = (E + P) r.
+  template <typename T>
+  HWENO_HD Eig<T> roe_eig(const T (&UL)[NC], const T (&UR)[NC]) const {
+    const T gm1 = T(gas - 1.0);
+    const T rl = rsqrt_nr(UL[0]), rr = rsqrt_nr(UR[0]);
+    const T a = rcp_nr(UL[0] * rl + UR[0] * rr);
+    const T ml = UL[1] * rl, mr = UR[1] * rr;                     // sqrt(rho) u
+    const T nl = DIM == 2 ? UL[2] * rl : T(0), nr = DIM == 2 ? UR[2] * rr : T(0);
+    const T pl = gm1 * (UL[E_] - T(0.5) * (ml * ml + nl * nl));
+    const T pr = gm1 * (UR[E_] - T(0.5) * (mr * mr + nr * nr));
+    Eig<T> e;
+    e.mu = (ml + mr) * a;
+    e.nu = (nl + nr) * a;
+    e.H = ((UL[E_] + pl) * rl + (UR[E_] + pr) * rr) * a;
+    e.k = T(0.5) * (e.mu * e.mu + e.nu * e.nu);
+    const T c2 = gm1 * (e.H - e.k);
+    e.ic = rsqrt_nr(c2);
+    e.c = c2 * e.ic;
+    e.b1 = gm1 * e.ic * e.ic;
+    e.b2 = e.b1 * e.k;
+    return e;
+  }
+
   template <int D, typename T>
   HWENO_HD void left(const Eig<T>& e, int j, T (&l)[NC]) const {
     const T vn = D == 0 ? e.mu : e.nu;    // normal velocity
@@ -535,6 +561,56 @@ HWENO_HD void hweno_cell_q(const Sys& sy, const Scheme& s, double h, double ih,
     sy.template unproject<D>(e, cl, uL);
     sy.template unproject<D>(e, ct, at);
   }
+}
+
+// The interface-basis switch (Jiang and Shu's decomposition): the right-face
+// value in the basis of Roe's matrix of (U0, Up), the left-face value in that
+// of (Um, U0), the modified derivative in the cell basis. Three projections
+// and three HWENO applications per cell instead of one (the smoothness
+// indicators differ per basis); each keeps only the output it is used for.
+template <int D, class Sys, typename T>
+HWENO_HD void hweno_cell_iface(const Sys& sy, const Scheme& s, double h, double ih,
+                               const typename Sys::template Prim<T>& q,
+                               const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
+                               const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
+                               const T (&Ap)[Sys::NC], T (&uR)[Sys::NC], T (&uL)[Sys::NC],
+                               T (&at)[Sys::NC]) {
+  constexpr int NC = Sys::NC;
+  if constexpr (!Sys::kChar) {
+    hweno_point<T>(Um[0], U0[0], Up[0], Am[0], Ap[0], s, h, ih, uR[0], uL[0], at[0]);
+  } else {
+    auto apply = [&](const auto& e, int which, T (&out)[NC]) {
+      T wm[NC], w0[NC], wp[NC], am[NC], ap[NC], c[NC];
+      sy.template project<D>(e, Um, wm);
+      sy.template project<D>(e, U0, w0);
+      sy.template project<D>(e, Up, wp);
+      sy.template project<D>(e, Am, am);
+      sy.template project<D>(e, Ap, ap);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        T r_, l_, t_;
+        hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, r_, l_, t_);
+        c[j] = which == 0 ? r_ : (which == 1 ? l_ : t_);
+      }
+      sy.template unproject<D>(e, c, out);
+    };
+    apply(sy.roe_eig(U0, Up), 0, uR);
+    apply(sy.roe_eig(Um, U0), 1, uL);
+    apply(sy.eig(q), 2, at);
+  }
+}
+
+// Either basis, by template flag.
+template <int D, bool IFACE, class Sys, typename T>
+HWENO_HD void hweno_cell_b(const Sys& sy, const Scheme& s, double h, double ih,
+                           const typename Sys::template Prim<T>& q, const T (&Um)[Sys::NC],
+                           const T (&U0)[Sys::NC], const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
+                           const T (&Ap)[Sys::NC], T (&uR)[Sys::NC], T (&uL)[Sys::NC],
+                           T (&at)[Sys::NC]) {
+  if constexpr (IFACE)
+    hweno_cell_iface<D>(sy, s, h, ih, q, Um, U0, Up, Am, Ap, uR, uL, at);
+  else
+    hweno_cell_q<D>(sy, s, h, ih, q, Um, U0, Up, Am, Ap, uR, uL, at);
 }
 
 // The same, computing the centre's primitive quantities itself.

@@ -42,6 +42,7 @@ struct StageArgs {
   int nx, ny, rows;                       // rows: output rows per block (2D)
   int plane;                              // nx * ny
   int bc[4];
+  int iface;                              // host side: interface characteristic basis
   Scheme s;
 };
 
@@ -68,7 +69,7 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) 
 // Outputs: residual parts -(F_{i+1/2} - F_{i-1/2})/dx of the u-, v- and
 // w-equations (the last from the mixed flux eta = f'(u) w), accumulated in
 // double, and the modified derivative v~. Valid on lanes 2..61.
-template <int NF, class Sys, typename T>
+template <int NF, bool IFACE, class Sys, typename T>
 __device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, double alpha,
                                         const T (&U)[Sys::NC], const T (&V)[Sys::NC],
                                         const T (&W)[Sys::NC], double (&RU)[Sys::NC],
@@ -87,7 +88,7 @@ __device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, double a
   // Step 1: HWENO once per cell -> u at both faces, v~ at the centre
   T uR[NC], uL[NC], vR[NC], vL[NC];
   const auto q = sy.prim(U);
-  hweno_cell_q<0>(sy, s, s.dx, s.idx, q, Um, U, Up, Vm, Vp, uR, uL, vt);
+  hweno_cell_b<0, IFACE>(sy, s, s.dx, s.idx, q, Um, U, Up, Vm, Vp, uR, uL, vt);
 #pragma unroll
   for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Vm[c], Vp[c], ih, vR[c], vL[c]);
   // pointwise f, h = f'(u) v, eta = f'(u) w at the cell centre
@@ -145,7 +146,7 @@ __device__ __forceinline__ double rk(double x, double base, double dt, double L)
 }
 
 // ------------------------------------------------------------ 1D stage kernel
-template <class Sys, typename T, int MODE>
+template <class Sys, typename T, int MODE, bool IFACE>
 __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   if (MODE != kRhs && A.active && *A.active == 0) return;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
   }
   double RU[NC], RV[NC], RW[NC];
   T vt[NC];
-  sweep_x<2>(sy, A.s, ax, U, V, W, RU, RV, RW, vt);
+  sweep_x<2, IFACE>(sy, A.s, ax, U, V, W, RU, RV, RW, vt);
   double smax = 0.0;
   unsigned flag = 0;
   if (out) {
@@ -234,8 +235,15 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol,
   }
 }
 
-template <class Sys, typename T, int MODE, bool WALLS>
+// VAR: kVarWalls (some boundary is reflective), kVarIface (interface basis);
+// each combination is its own instantiation, so the common one carries no
+// code of the others.
+constexpr int kVarWalls = 1, kVarIface = 2;
+
+template <class Sys, typename T, int MODE, int VAR>
 __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
+  constexpr bool WALLS = (VAR & kVarWalls) != 0;
+  constexpr bool IFACE = (VAR & kVarIface) != 0;
   constexpr int NC = Sys::NC;
   if (MODE != kRhs && A.active && *A.active == 0) return;
   const Scheme& s = A.s;
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
     T mG[NC], mT[NC], pG[NC], pT[NC], wtn[NC];
     if (r >= y0) {
       T uT[NC], uB[NC], wT[NC], wB[NC];
-      hweno_cell<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, uT, uB, wtn);
+      hweno_cell_b<1, IFACE>(sy, s, s.dy, s.idy, sy.prim(Ub), Ua, Ub, Uc, Wa, Wc, uT, uB, wtn);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_derivs(Ua[c], Ub[c], Uc[c], Wa[c], Wc[c], ihy, wT[c], wB[c]);
       T gt[NC], tt[NC], gb[NC], tb[NC];
@@ -352,7 +360,7 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
         const int o = r - 2;
         double RU[NC], RV[NC], RW[NC];
         T vt[NC];
-        sweep_x<3>(sy, s, ax, Ua, Va, Wa, RU, RV, RW, vt);
+        sweep_x<3, IFACE>(sy, s, ax, Ua, Va, Wa, RU, RV, RW, vt);
         if (out_col) {
           T Unew[NC];
 #pragma unroll
@@ -1127,6 +1135,8 @@ hweno_status validate(const hweno_problem* p) {
   if (p->dim == 2 && (p->bc[2] == HWENO_PERIODIC) != (p->bc[3] == HWENO_PERIODIC))
     return HWENO_EINVAL;
   if (p->precision != HWENO_F64 && p->precision != HWENO_F32) return HWENO_EINVAL;
+  if (p->char_basis != HWENO_BASIS_CELL && p->char_basis != HWENO_BASIS_INTERFACE)
+    return HWENO_EINVAL;
   const int nc = p->system == HWENO_EULER ? p->dim + 2 : 1;
   // 32-bit element offsets inside a state array
   if ((double)nc * (double)p->nx * (double)p->ny >= 2147483647.0) return HWENO_EINVAL;
@@ -1297,11 +1307,22 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
   StageArgs<T> A = A0;
   if constexpr (DIM == 1) {
     dim3 grid((A.nx + kXOut - 1) / kXOut);
-    switch (mode) {
-      case kRhs: stage1d_kernel<Sys, T, kRhs><<<grid, kWave, 0, st>>>(A, sy); break;
-      case kStage1: stage1d_kernel<Sys, T, kStage1><<<grid, kWave, 0, st>>>(A, sy); break;
-      case kStage2: stage1d_kernel<Sys, T, kStage2><<<grid, kWave, 0, st>>>(A, sy); break;
-      default: stage1d_kernel<Sys, T, kStage3><<<grid, kWave, 0, st>>>(A, sy); break;
+    auto modes = [&](auto iface) {
+      constexpr bool I = decltype(iface)::value;
+      switch (mode) {
+        case kRhs: stage1d_kernel<Sys, T, kRhs, I><<<grid, kWave, 0, st>>>(A, sy); break;
+        case kStage1: stage1d_kernel<Sys, T, kStage1, I><<<grid, kWave, 0, st>>>(A, sy); break;
+        case kStage2: stage1d_kernel<Sys, T, kStage2, I><<<grid, kWave, 0, st>>>(A, sy); break;
+        default: stage1d_kernel<Sys, T, kStage3, I><<<grid, kWave, 0, st>>>(A, sy); break;
+      }
+    };
+    if constexpr (Sys::kChar) {
+      if (A.iface)
+        modes(std::true_type{});
+      else
+        modes(std::false_type{});
+    } else {
+      modes(std::false_type{});
     }
   } else {
     auto go = [&](auto kernel, auto tag) {
@@ -1313,25 +1334,28 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
       dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
       kernel<<<grid, kWave, 0, st>>>(A, sy);
     };
-    auto modes = [&](auto walls) {
-      constexpr bool W = decltype(walls)::value;
-      constexpr int kT = W ? 16 : 0;   // separate occupancy cache entries
+    auto modes = [&](auto var) {
+      constexpr int V = decltype(var)::value;
+      constexpr int kT = 16 * V;   // separate occupancy cache entries
       switch (mode) {
-        case kRhs: go(stage2d_kernel<Sys, T, kRhs, W>, std::integral_constant<int, kRhs + kT>{}); break;
-        case kStage1: go(stage2d_kernel<Sys, T, kStage1, W>, std::integral_constant<int, kStage1 + kT>{}); break;
-        case kStage2: go(stage2d_kernel<Sys, T, kStage2, W>, std::integral_constant<int, kStage2 + kT>{}); break;
-        default: go(stage2d_kernel<Sys, T, kStage3, W>, std::integral_constant<int, kStage3 + kT>{}); break;
+        case kRhs: go(stage2d_kernel<Sys, T, kRhs, V>, std::integral_constant<int, kRhs + kT>{}); break;
+        case kStage1: go(stage2d_kernel<Sys, T, kStage1, V>, std::integral_constant<int, kStage1 + kT>{}); break;
+        case kStage2: go(stage2d_kernel<Sys, T, kStage2, V>, std::integral_constant<int, kStage2 + kT>{}); break;
+        default: go(stage2d_kernel<Sys, T, kStage3, V>, std::integral_constant<int, kStage3 + kT>{}); break;
       }
     };
     bool walls = false;
     for (int k = 0; k < 4; ++k) walls = walls || A.bc[k] == kBcReflective;
     if constexpr (Sys::kChar) {
-      if (walls)
-        modes(std::true_type{});
-      else
-        modes(std::false_type{});
+      const int var = (walls ? kVarWalls : 0) | (A.iface ? kVarIface : 0);
+      switch (var) {
+        case 0: modes(std::integral_constant<int, 0>{}); break;
+        case kVarWalls: modes(std::integral_constant<int, kVarWalls>{}); break;
+        case kVarIface: modes(std::integral_constant<int, kVarIface>{}); break;
+        default: modes(std::integral_constant<int, kVarWalls | kVarIface>{}); break;
+      }
     } else {
-      modes(std::false_type{});
+      modes(std::integral_constant<int, 0>{});
     }
   }
   return check_launch();
@@ -1346,6 +1370,7 @@ StageArgs<T> base_args(const hweno_problem* p) {
   A.rows = kRowsPerBlock;
   A.plane = p->nx * p->ny;
   for (int k = 0; k < 4; ++k) A.bc[k] = p->bc[k];
+  A.iface = p->char_basis == HWENO_BASIS_INTERFACE;
   A.s = make_scheme(p);
   return A;
 }
@@ -1729,6 +1754,7 @@ hweno_status hweno_adjoint_step(const hweno_problem* p, const void* u_n, const v
   const bool two = p->dim == 2;
   if (!u_n || !v_n || !dt || !alpha_rec || !lam_u_in || !lam_v_in || !lam_u_out || !lam_v_out || !ws)
     return HWENO_EINVAL;
+  if (p->system == HWENO_EULER && p->char_basis == HWENO_BASIS_INTERFACE) return HWENO_EUNSUPPORTED;
   if (two && (!w_n || !lam_w_in || !lam_w_out)) return HWENO_EINVAL;
   if (!two && (w_n || lam_w_in || lam_w_out)) return HWENO_EINVAL;
   const void* ins[8] = {u_n, v_n, w_n, stages, lam_u_in, lam_v_in, lam_w_in, nullptr};

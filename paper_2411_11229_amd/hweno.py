@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, 'libhweno.so')
 SYSTEMS = {'advection': 0, 'burgers': 1, 'euler': 2}
 BCS = {'periodic': 0, 'transmissive': 1, 'reflective': 2}
 PRECISIONS = {'f64': 0, 'f32': 1}
+BASES = {'cell': 0, 'interface': 1}
 DT_RULES = {'production': 0, 'accuracy': 1, 'fixed': 2}
 STATUS = {0: 'ok', -1: 'invalid argument', -2: 'unsupported', -3: 'HIP runtime error',
           -4: 'non-finite state', -5: 'non-physical state'}
@@ -37,7 +38,8 @@ class _CProblem(ctypes.Structure):
                 ('adv_a', ctypes.c_double), ('adv_b', ctypes.c_double),
                 ('gas_gamma', ctypes.c_double), ('gamma0', ctypes.c_double),
                 ('d0', ctypes.c_double), ('eps', ctypes.c_double),
-                ('bc', ctypes.c_int32 * 4), ('precision', ctypes.c_int32)]
+                ('bc', ctypes.c_int32 * 4), ('precision', ctypes.c_int32),
+                ('char_basis', ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -99,6 +101,7 @@ class Problem:
     eps: float = 1e-10
     bc: tuple = ('periodic',) * 4
     precision: str = 'f64'
+    basis: str = 'cell'               # characteristic basis: 'cell' | 'interface'
 
     def __post_init__(self):
         if self.gamma0 is None:
@@ -126,6 +129,7 @@ class Problem:
         for k in range(4):
             p.bc[k] = BCS[self.bc[k]]
         p.precision = PRECISIONS[self.precision]
+        p.char_basis = BASES[self.basis]
         return p
 
 

@@ -80,8 +80,13 @@ def test_reflective_walls_accepted_for_euler(lib, bc):
     assert _ws_bytes(lib, _prob(dim=1, ny=1, bc=bc))[0] == 0
 
 
+def test_interface_basis_accepted(lib):
+    assert _ws_bytes(lib, _prob(basis='interface'))[0] == 0
+    assert _ws_bytes(lib, _prob(system='burgers', basis='interface'))[0] == 0
+
+
 def test_invalid_enum_values_rejected(lib):
-    for field, val in (('system', 7), ('precision', 2)):
+    for field, val in (('system', 7), ('precision', 2), ('char_basis', 2), ('char_basis', -1)):
         p = _prob()
         setattr(p, field, val)
         assert _ws_bytes(lib, p)[0] == -1

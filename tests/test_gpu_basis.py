@@ -1,0 +1,150 @@
+"""The interface-basis switch (Jiang and Shu's characteristic decomposition:
+face values in the eigenvectors of Roe's matrix of the two cells sharing the
+face, the modified derivative in the cell basis) on the HIP path against the
+FP64 oracle, with the tolerances of the cell-basis parity tests; and the
+adjoint's refusal of it."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hweno as O
+from paper_2411_11229_amd import workloads as WL
+
+from test_gpu_parity import (RTOL64, check_run, dev, f32_bounds, host, oprob, oracle_sensitivity,
+                             solver)
+
+pytestmark = pytest.mark.gpu
+
+IF = dict(basis='interface')
+
+
+def cases():
+    return [
+        ('euler1d-smooth-200', WL.random_smooth_1d(200, 'euler', seed=81)),
+        ('euler1d-riemann-2000', WL.euler1d_riemann_sine(2000, seed=2000)),
+        ('euler1d-riemann-97', WL.euler1d_riemann_sine(97, seed=2001)),
+        ('euler1d-blast-800', WL.blast_wave_1d(800)),
+        ('euler2d-smooth-130x70', WL.euler2d_smooth(130, seed=3302, ny=70)),
+        ('euler2d-quadrants-96x80', WL.euler2d_quadrants(96, seed=4302, ny=80)),
+        ('euler2d-quadrants-walls-61x48', WL.with_bc(WL.euler2d_quadrants(61, seed=4303, ny=48),
+                                                     ('reflective',) * 4)),
+        ('euler2d-min-5x5', WL.euler2d_smooth(5, seed=3303)),
+    ]
+
+
+def _scale(w, k, r):
+    """Per-output scale: the field's max; for the modified derivatives also
+    the candidate derivatives they combine (as in the wall tests)."""
+    scale = np.max(np.abs(r))
+    if k >= 3:
+        ax, h, D = (-1, w.dx, w.V) if k == 3 else (-2, w.dy, w.W)
+        scale = max(scale, np.max(np.abs(np.diff(w.U, axis=ax))) / h, np.max(np.abs(D)))
+    return scale
+
+
+@pytest.mark.parametrize("name,w", cases(), ids=[c[0] for c in cases()])
+def test_interface_basis_rhs_matches_oracle_f64(name, w):
+    print(f'case {name}', flush=True)
+    s = solver(w, **IF)
+    p = oprob(w, **IF)
+    alpha = O.max_speed(p, w.U)
+    ref = O.rhs(p, w.U, w.V, w.W, alpha)
+    cell = O.rhs(oprob(w), w.U, w.V, w.W, alpha)
+    two = w.dim == 2
+    got = s.rhs(dev(w.U), dev(w.V), dev(w.W) if two else None, dev(np.array(alpha)))
+    moved = 0.0
+    for k, (g, r, c) in enumerate(zip(got, ref, cell)):
+        if r is None:
+            continue
+        sc = _scale(w, k, r)
+        e = np.max(np.abs(host(g) - r)) / sc
+        moved = max(moved, np.max(np.abs(r - c)) / sc)
+        print(f'  output {k}: rel err {e:.3e}')
+        assert e <= RTOL64, f'{name} output {k}: {e:.3e}'
+    print(f'  interface vs cell basis (oracle): {moved:.3e}')
+
+
+@pytest.mark.parametrize("name,w", [cases()[1], cases()[5]], ids=[cases()[k][0] for k in (1, 5)])
+def test_interface_basis_rhs_f32(name, w):
+    two = w.dim == 2
+    w.U = w.U.astype(np.float32).astype(np.float64)
+    w.V = w.V.astype(np.float32).astype(np.float64)
+    w.W = w.W.astype(np.float32).astype(np.float64) if two else None
+    s = solver(w, precision='f32', **IF)
+    p = oprob(w, **IF)
+    alpha = O.max_speed(p, w.U)
+    f32 = lambda a: dev(a, torch.float32)
+    got = s.rhs(f32(w.U), f32(w.V), f32(w.W) if two else None, dev(np.array(alpha)))
+    ref = O.rhs(p, w.U, w.V, w.W, alpha)
+    tol = f32_bounds(w, alpha)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        if r is None:
+            continue
+        err = np.max(np.abs(host(g) - r))
+        print(f'  output {k}: abs err {err:.3e}  bound {tol[k]:.3e}')
+        assert err <= tol[k], f'output {k}: abs err {err:.3e} > bound {tol[k]:.3e}'
+
+
+@pytest.mark.parametrize("name,w", [cases()[k] for k in (1, 4, 5, 6)],
+                         ids=[cases()[k][0] for k in (1, 4, 5, 6)])
+def test_interface_basis_step_matches_oracle_f64(name, w):
+    s = solver(w, **IF)
+    p = oprob(w, **IF)
+    two = w.dim == 2
+    U, V = dev(w.U), dev(w.V)
+    W = dev(w.W) if two else None
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dt = torch.zeros(1, dtype=torch.float64, device='cuda')
+    s.step(U, V, W, t, 1e9, dt_used=dt)
+    alpha = O.max_speed(p, w.U)
+    dto = O.time_step(p, alpha)
+    assert float(dt.item()) == pytest.approx(dto, rel=1e-14)
+    Uo, Vo, Wo, _ = O.step(p, w.U, w.V, w.W, dto, (alpha, None, None))
+    for k, (g, r) in enumerate(zip((U, V, W), (Uo, Vo, Wo))):
+        if r is None:
+            continue
+        e = np.max(np.abs(host(g) - r)) / np.max(np.abs(r))
+        print(f'  field {k}: rel err {e:.3e}')
+        assert e <= RTOL64, f'{name} field {k}: {e:.3e}'
+
+
+@pytest.mark.parametrize("name,w,steps", [
+    ('euler1d-riemann-2000', WL.euler1d_riemann_sine(2000, seed=2003), 60),
+    ('euler2d-quadrants-64x48', WL.euler2d_quadrants(64, seed=4304, ny=48), 15)],
+    ids=['euler1d-riemann-2000', 'euler2d-quadrants-64x48'])
+def test_interface_basis_run_matches_oracle(name, w, steps):
+    s = solver(w, **IF)
+    two = w.dim == 2
+    U, V = dev(w.U), dev(w.V)
+    W = dev(w.W) if two else None
+    n, t, dts = s.run(U, V, W, t_end=1e9, max_steps=steps)
+    p = oprob(w, **IF)
+    k = 3 if two else 2
+    logs = []
+
+    def run(a, b, c):
+        out = O.run(p, a, b, c, 1e9, max_steps=steps)
+        logs.append(np.array(out[3].dts))
+        return out[:k]
+    base, worst = oracle_sensitivity(p, w, run)
+    check_run(w, (U, V, W)[:k], base, worst, f'{name}-interface')
+    # dt follows the state's wave speed, which diverges with the state: the
+    # same 10x-of-the-oracle's-own-divergence rule
+    dt_div = max(np.max(np.abs(l - logs[0]) / logs[0]) for l in logs[1:])
+    e = np.max(np.abs(host(dts) - logs[0]) / logs[0])
+    print(f'  dt rel err {e:.3e}  oracle 1-ulp divergence {dt_div:.3e}')
+    assert e <= max(10 * dt_div, 1e-12)
+    s.health()
+
+
+def test_adjoint_rejects_interface_basis():
+    from paper_2411_11229_amd import hweno
+    w = WL.euler2d_smooth(16, seed=3304, ny=12)
+    s = solver(w, **IF)
+    X = [dev(w.U), dev(w.V), dev(w.W)]
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device='cuda')
+    rec = torch.ones(6, dtype=torch.float64, device='cuda')
+    out = [torch.empty_like(x) for x in X]
+    with pytest.raises(hweno.HwenoError) as ei:
+        s.adjoint_step(X[0], X[1], X[2], dt, rec, [x.clone() for x in X], out)
+    assert ei.value.code == -2
