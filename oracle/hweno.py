@@ -35,6 +35,10 @@ notes of the repository):
   * Characteristic basis switch ('interface'): u^-_{i+1/2} and u^+_{i+1/2}
     in the eigenvectors of Roe's average of U_i, U_{i+1} (Jiang and Shu);
     v~ keeps the cell basis.
+  * Dirichlet boundary ('dirichlet', the fixed top and bottom states of
+    Example 4.11): both ghost cells hold the given state, the derivatives 0.
+  * Source term (euler2d-s): S(u) added to L^1, S(v) and S(w) to the
+    derivative equations (S is linear in u).
   * Reflective boundary (Euler only): mirror cells with the sign rules of
     (RBC-1d), (RBC-2d-x), (RBC-2d-y); ghost -1-k is the image of cell k.
 """
@@ -70,6 +74,8 @@ class Problem:
     eps: float = 1e-10
     bc: tuple = ('periodic', 'periodic', 'periodic', 'periodic')  # x_lo x_hi y_lo y_hi
     basis: str = 'cell'             # characteristic basis: 'cell' | 'interface'
+    bc_state: tuple = (None, None, None, None)   # conserved ghost state of 'dirichlet' sides
+    gravity: float = 0.0            # g of the source term (euler2d-s), 2D Euler only
 
     def __post_init__(self):
         if self.gamma0 is None:
@@ -288,16 +294,19 @@ def reflect_signs(sys, d):
     return (sU, sV, sW) if d == 0 else (sU, sW, sV)
 
 
-def pad(a, bc_lo, bc_hi, axis=-1, sign=None):
+def pad(a, bc_lo, bc_hi, axis=-1, sign=None, fixed=(None, None)):
     """Add NG ghost cells on both ends of ``axis`` (the last one for the
-    reflective rule). 'periodic' wraps; 'transmissive' copies the nearest
-    interior cell (zero-order extrapolation of U and of its derivatives);
-    'reflective' takes the mirror cell (ghost -1-k is the image of cell k,
-    ghost n+k of cell n-1-k) with component c multiplied by sign[c]."""
+    reflective and fixed rules). 'periodic' wraps; 'transmissive' copies the
+    nearest interior cell (zero-order extrapolation of U and of its
+    derivatives); 'reflective' takes the mirror cell (ghost -1-k is the image
+    of cell k, ghost n+k of cell n-1-k) with component c multiplied by
+    sign[c]; 'dirichlet' puts the side's given value (fixed[0] below,
+    fixed[1] above: a per-component sequence) in both ghost cells."""
     xp = _array.ns(a)
     n = a.shape[axis]
-    idx, flip = [], []
+    idx, flip, fix = [], [], []
     for i in range(-NG, n + NG):
+        fix.append(None)
         if 0 <= i < n:
             idx.append(i)
             flip.append(False)
@@ -311,10 +320,25 @@ def pad(a, bc_lo, bc_hi, axis=-1, sign=None):
             if sign is None:
                 raise ValueError('reflective walls are defined for the Euler equations only')
             idx.append(-1 - i if i < 0 else 2 * n - 1 - i)
+        elif side == 'dirichlet':
+            idx.append(0)
+            fix[-1] = fixed[0] if i < 0 else fixed[1]
+            if fix[-1] is None:
+                raise ValueError('dirichlet side without a state')
         else:
             raise ValueError(side)
         flip.append(side == 'reflective')
     out = xp.take(a, idx, axis)
+    if any(f is not None for f in fix):
+        assert axis in (-1, a.ndim - 1)
+        keep = np.ones((a.shape[0], len(idx)))
+        add = np.zeros((a.shape[0], len(idx)))
+        for j, f in enumerate(fix):
+            if f is not None:
+                keep[:, j] = 0.0
+                add[:, j] = f
+        shape = (a.shape[0],) + (1,) * (a.ndim - 2) + (len(idx),)
+        out = out * xp.const(keep.reshape(shape), a) + xp.const(add.reshape(shape), a)
     if not any(flip):
         return out
     assert axis in (-1, a.ndim - 1)
@@ -438,7 +462,8 @@ def lax_friedrichs(fm, fp, um, up, alpha):
 # ----------------------------------------------------------------------------
 # One directional sweep: Steps 1-3 of section 2 (and Steps 1/2 of section 3)
 # ----------------------------------------------------------------------------
-def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis='cell'):
+def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis='cell',
+          state=(None, None)):
     """HWENO-I procedure along the last axis for direction ``d``.
 
     U: state; A: derivative along the sweep (v for x, w for y); B: the other
@@ -450,8 +475,9 @@ def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis=
     xp = _array.ns(U)
     n = U.shape[-1]
     sU, sA, sB = reflect_signs(sys, d)
-    Up = pad(U, bc_lo, bc_hi, sign=sU)
-    Ap = pad(A, bc_lo, bc_hi, sign=sA)
+    zero = [0.0] * U.shape[0]
+    Up = pad(U, bc_lo, bc_hi, sign=sU, fixed=state)
+    Ap = pad(A, bc_lo, bc_hi, sign=sA, fixed=(zero, zero))
     # HWENO on cells -1..n (padded 1..n+2): interfaces -1/2..n-1/2 need them
     m, c, p = (slice(0, n + 2), slice(1, n + 3), slice(2, n + 4))
     Um, U0, Upl = Up[..., m], Up[..., c], Up[..., p]
@@ -497,7 +523,7 @@ def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis=
     RA = -(Hh[..., 1:] - Hh[..., :-1]) / h
     RB = None
     if B is not None:
-        Bp = pad(B, bc_lo, bc_hi, sign=sB)
+        Bp = pad(B, bc_lo, bc_hi, sign=sB, fixed=(zero, zero))
         e = sys.jac_apply(Up, Bp, d)
         Eh = mixed_flux(e[..., q[0]], e[..., q[1]], e[..., q[2]], e[..., q[3]])
         RB = -(Eh[..., 1:] - Eh[..., :-1]) / h
@@ -524,17 +550,35 @@ def rhs(prob, U, V, W=None, alpha=None):
         alpha = max_speed(prob, U)
     g, dl, eps, bs = prob.linear_gamma, prob.linear_d, prob.eps, prob.basis
     bx0, bx1, by0, by1 = prob.bc
+    st = prob.bc_state
     if prob.dim == 1:
-        L1, L2, _, vt = sweep(sys, 0, U, V, None, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs)
+        L1, L2, _, vt = sweep(sys, 0, U, V, None, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs,
+                              (st[0], st[1]))
         return L1, L2, None, vt, None
     xp = _array.ns(U)
     # Step 1: x-direction on (u, v); mixed flux eta = f'(u) w
-    Lx1, Lx2, Lx3, vt = sweep(sys, 0, U, V, W, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs)
+    Lx1, Lx2, Lx3, vt = sweep(sys, 0, U, V, W, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs,
+                              (st[0], st[1]))
     # Step 2: y-direction on (u, w); mixed flux xi = g'(u) v
     t = lambda a: xp.moveaxis(a, -1, -2)
-    Ly1, Ly3, Ly2, wt = sweep(sys, 1, t(U), t(W), t(V), prob.dy, alpha[1], by0, by1, g, dl, eps, bs)
+    Ly1, Ly3, Ly2, wt = sweep(sys, 1, t(U), t(W), t(V), prob.dy, alpha[1], by0, by1, g, dl, eps, bs,
+                              (st[2], st[3]))
     # Step 4
-    return Lx1 + t(Ly1), Lx2 + t(Ly2), Lx3 + t(Ly3), vt, t(wt)
+    L1, L2, L3 = Lx1 + t(Ly1), Lx2 + t(Ly2), Lx3 + t(Ly3)
+    if prob.gravity != 0.0:
+        L1, L2, L3 = L1 + gravity_source(prob, U), L2 + gravity_source(prob, V), L3 + gravity_source(prob, W)
+    return L1, L2, L3, vt, t(wt)
+
+
+def gravity_source(prob, X):
+    """The source of (euler2d-s), S(U) = g (0, 0, rho, rho v). It is linear in
+    U, so the equations of the derivatives v = u_x, w = u_y (obtained by
+    differentiating (euler2d-s)) carry S(v) and S(w)."""
+    if prob.system != 'euler' or prob.dim != 2:
+        raise ValueError('the gravity source is defined for the 2D Euler equations')
+    xp = _array.ns(X)
+    z = 0.0 * X[0]
+    return xp.stack([z, z, prob.gravity * X[0], prob.gravity * X[2]])
 
 
 # ----------------------------------------------------------------------------

@@ -20,6 +20,7 @@ stand-ins with the shapes and value ranges of its examples):
   * ``mach2000_initial`` the initial state of Example 4.10 (time-step pin).
   * ``blast_wave_1d``    Example 4.4 (Woodward-Colella blast waves between
     two reflective walls).
+  * ``rayleigh_taylor``  Example 4.11 (gravity source, walls, fixed states).
   * ``with_bc``          any of the above with other boundary conditions.
 """
 import math
@@ -49,12 +50,19 @@ class Workload:
     x: np.ndarray = None
     y: np.ndarray = None
     extra: dict = field(default_factory=dict)
+    bc_state: tuple = (None, None, None, None)   # conserved states of 'dirichlet' sides
+    gravity: float = 0.0
 
     def problem_kwargs(self):
         """Keyword arguments shared by the oracle's Problem and the binding."""
-        return dict(dim=self.dim, nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy,
-                    system=self.system, adv_a=self.adv_a, adv_b=self.adv_b,
-                    gas_gamma=self.gas_gamma, bc=tuple(self.bc))
+        kw = dict(dim=self.dim, nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy,
+                  system=self.system, adv_a=self.adv_a, adv_b=self.adv_b,
+                  gas_gamma=self.gas_gamma, bc=tuple(self.bc))
+        if any(b is not None for b in self.bc_state):
+            kw['bc_state'] = tuple(self.bc_state)
+        if self.gravity != 0.0:
+            kw['gravity'] = self.gravity
+        return kw
 
 
 def centres(n, lo, hi):
@@ -137,6 +145,37 @@ def blast_wave_1d(n=800, g=1.4):
     return Workload('blast_wave_1d', 1, 'euler', n, 1, h, 1.0, U, V, None,
                     bc=('reflective', 'reflective', 'periodic', 'periodic'), gas_gamma=g,
                     t_end=0.038, x=x)
+
+
+def rayleigh_taylor(nx=60, g=5.0 / 3.0):
+    """Example 4.11 on [0, 0.25] x [0, 1] with nx x 4nx cells: heavy fluid
+    (rho = 2, P = 2y + 1) below y = 1/2, light fluid (rho = 1, P = y + 3/2)
+    above, v = -0.025 c cos(8 pi x) with c = sqrt(g P / rho); gravity 1 in +y
+    (the source of (euler2d-s)); reflective walls left and right, the fixed
+    states (2, 0, 0, 1) below and (1, 0, 0, 2.5) above; T = 1.95. V, W are the
+    exact derivatives away from the interface (zero jump contribution)."""
+    ny = 4 * nx
+    x, hx = centres(nx, 0.0, 0.25)
+    y, hy = centres(ny, 0.0, 1.0)
+    X, Y = np.meshgrid(x, y)
+    low = Y < 0.5
+    rho = np.where(low, 2.0, 1.0)
+    p = np.where(low, 2.0 * Y + 1.0, Y + 1.5)
+    py = np.where(low, 2.0, 1.0)
+    c = np.sqrt(g * p / rho)
+    cy = g * py / (2.0 * rho * c)
+    cosx, sinx = np.cos(8 * math.pi * X), np.sin(8 * math.pi * X)
+    v = -0.025 * c * cosx
+    vx = 0.025 * c * 8 * math.pi * sinx
+    vy = -0.025 * cy * cosx
+    zero = np.zeros_like(X)
+    U, V = conserved_2d(rho, zero, v, p, zero, zero, vx, zero, g)
+    _, W = conserved_2d(rho, zero, v, p, zero, zero, vy, py, g)
+    cons = lambda r, pp: (r, 0.0, 0.0, pp / (g - 1.0))
+    return Workload('rayleigh_taylor', 2, 'euler', nx, ny, hx, hy, U, V, W,
+                    bc=('reflective', 'reflective', 'dirichlet', 'dirichlet'), gas_gamma=g,
+                    t_end=1.95, x=x, y=y, bc_state=(None, None, cons(2.0, 1.0), cons(1.0, 2.5)),
+                    gravity=1.0)
 
 
 def with_bc(w, bc):

@@ -18,6 +18,8 @@ def _setup(kind):
     elif kind == 'euler2d-reflective':
         w = WL.with_bc(WL.euler2d_smooth(10, seed=3102, ny=9),
                        ('reflective', 'transmissive', 'reflective', 'reflective'))
+    elif kind == 'rayleigh-taylor':
+        w = WL.rayleigh_taylor(6)
     elif kind == 'euler1d':
         w = WL.euler1d_riemann_sine(24, seed=2010)
     elif kind == 'euler1d-reflective':
@@ -36,7 +38,7 @@ def _loss(p, w, log, U, V, W, target):
 
 
 @pytest.mark.parametrize("kind", ["euler1d", "euler1d-reflective", "euler2d",
-                                  "euler2d-reflective", "burgers2d"])
+                                  "euler2d-reflective", "rayleigh-taylor", "burgers2d"])
 def test_torch_oracle_gradient_matches_finite_differences(kind):
     w, p, log = _setup(kind)
     rng = np.random.default_rng(5)
