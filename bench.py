@@ -262,6 +262,31 @@ def basis_robustness():
     return out
 
 
+def rayleigh_taylor_times():
+    """Example 4.11 (gravity source, walls, fixed states) to t = 1.95 at the
+    paper's three meshes, FP64, wall time per run (inputs resident; one
+    warm-up run of 20 steps first)."""
+    import torch
+    from paper_2411_11229_amd import hweno, workloads
+    out = {}
+    for nx in (60, 120, 240):
+        w = workloads.rayleigh_taylor(nx)
+        s = hweno.Solver(hweno.Problem(**w.problem_kwargs()))
+        d = lambda a: torch.tensor(a, dtype=torch.float64, device='cuda')
+        U, V, W = d(w.U), d(w.V), d(w.W)
+        s.run(U.clone(), V.clone(), W.clone(), t_end=w.t_end, max_steps=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n, t, _ = s.run(U, V, W, t_end=w.t_end)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.health()
+        out[f'{nx}x{4 * nx}'] = dict(steps=n, t=t, wall_s=wall,
+                                     cell_stage_updates_per_s=nx * 4 * nx * 3 * n / wall)
+        print(json.dumps({f'{nx}x{4 * nx}': out[f'{nx}x{4 * nx}']}), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument('--gpus', type=int, default=1)
@@ -276,6 +301,8 @@ def main():
     ap.add_argument('--probe', choices=['copy'], help='run a calibration probe instead')
     ap.add_argument('--basis-robustness', action='store_true',
                     help='compare the cell and interface characteristic bases instead')
+    ap.add_argument('--rayleigh-taylor', action='store_true',
+                    help='time the Rayleigh-Taylor example at the paper\'s meshes instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
                     help='precision of the headline run')
     args = ap.parse_args()
@@ -297,6 +324,9 @@ def main():
         return
     if args.basis_robustness:
         print(json.dumps({'basis_robustness': basis_robustness()}))
+        return
+    if args.rayleigh_taylor:
+        print(json.dumps({'rayleigh_taylor': rayleigh_taylor_times()}))
         return
 
     main_run = time_forward(args.n, args.precision, args.steps, args.warmup)

@@ -64,9 +64,14 @@ typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_s
  *                 mirror image of cell k (ghost n+k of cell n-1-k) with the
  *                 normal momentum negated; the derivative along the wall
  *                 normal has every other component negated, the derivative
- *                 along the wall follows the state. HWENO_EULER only.
+ *                 along the wall follows the state. HWENO_EULER only;
+ *   dirichlet     a fixed state (the top and bottom boundaries of Example
+ *                 4.11): both ghost cells hold bc_state[side] (conserved
+ *                 variables), the derivatives v, w are 0 there.
  * The two ends of an axis are independent except for periodic. */
-typedef enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2 } hweno_bc;
+typedef enum {
+  HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2, HWENO_DIRICHLET = 3
+} hweno_bc;
 typedef enum { HWENO_F64 = 0, HWENO_F32 = 1 } hweno_precision;
 /* Characteristic basis of the HWENO interpolation for the Euler systems
  * (remark on systems in section 2, local characteristic decomposition):
@@ -91,7 +96,10 @@ typedef enum {
  * E = P/(gas_gamma - 1) + rho |vel|^2 / 2), the linear weights of (interp)
  * (gamma0; gamma1 = gamma2 = (1 - gamma0)/2) and of (limiter) (d0;
  * d1 = d2 = (1 - d0)/2), and epsilon of (nonlinear). The paper uses
- * gamma0 = 0.95 (1D) / 0.99 (2D), d0 = 0.9, eps = 1e-10.
+ * gamma0 = 0.95 (1D) / 0.99 (2D), d0 = 0.9, eps = 1e-10. `gravity` is g of
+ * the source term of (euler2d-s), S(U) = g (0, 0, rho, rho v) (2D Euler
+ * only; 0 = no source); S is linear, so the derivative equations carry
+ * S(v) and S(w).
  */
 typedef struct {
   int32_t dim;          /* 1 or 2                                                */
@@ -106,6 +114,10 @@ typedef struct {
   int32_t bc[4];        /* hweno_bc at x_lo, x_hi, y_lo, y_hi (see hweno_bc)      */
   int32_t precision;    /* hweno_precision of every array argument                */
   int32_t char_basis;   /* hweno_char_basis                                       */
+  double bc_state[4][4];/* conserved state of each HWENO_DIRICHLET side (x_lo,     */
+                        /* x_hi, y_lo, y_hi), first ncomp entries; finite, and    */
+                        /* rho, P > 0 for Euler                                   */
+  double gravity;       /* g of (euler2d-s); 0 unless system == EULER, dim == 2   */
 } hweno_problem;
 
 /* Human-readable name of a status code (static string). */

@@ -624,13 +624,14 @@ HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
 
 // ------------------------------------------------------------- index maps
 // Boundary codes, as in the C ABI.
-constexpr int kBcPeriodic = 0, kBcTransmissive = 1, kBcReflective = 2;
+constexpr int kBcPeriodic = 0, kBcTransmissive = 1, kBcReflective = 2, kBcDirichlet = 3;
 
 // Ghost cells by index map: periodic wraps, transmissive clamps (copies the
 // nearest interior cell), reflective mirrors (ghost -1-k is the image of
 // cell k, ghost n+k of cell n-1-k). Any integer i is accepted and the result
 // is always in [0, n): lanes further out than the mirror reaches (only the
 // two ghosts next to a wall enter the scheme) are clamped to an edge cell.
+// Fixed-state (Dirichlet) ghosts are clamped too; their values are replaced.
 HWENO_HD int map_index(int i, int n, int lo, int hi) {
   if (i >= 0 && i < n) return i;
   const int side = i < 0 ? lo : hi;
@@ -643,6 +644,13 @@ HWENO_HD int map_index(int i, int n, int lo, int hi) {
     return m < 0 ? 0 : (m > n - 1 ? n - 1 : m);
   }
   return i < 0 ? 0 : n - 1;
+}
+
+// The side (0 low, 1 high) whose fixed state a ghost cell holds, or -1.
+HWENO_HD int fixed_side(int i, int n, int lo, int hi) {
+  if (i < 0 && lo == kBcDirichlet) return 0;
+  if (i >= n && hi == kBcDirichlet) return 1;
+  return -1;
 }
 
 // True for a ghost cell behind a reflective wall.

@@ -43,6 +43,8 @@ struct StageArgs {
   int plane;                              // nx * ny
   int bc[4];
   int iface;                              // host side: interface characteristic basis
+  double gs[4][4];                        // fixed (Dirichlet) ghost states per side
+  double gravity;                         // g of the (euler2d-s) source
   Scheme s;
 };
 
@@ -170,6 +172,14 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
     const bool m = mirrored(col, A.nx, A.bc[0], A.bc[1]);
     mirror_state<Sys, 0>(m, U);
     mirror_normal_derivative<Sys, 0>(m, V);
+    const int fs = fixed_side(col, A.nx, A.bc[0], A.bc[1]);
+    if (fs >= 0) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        U[c] = T(A.gs[fs][c]);
+        V[c] = T(0);
+      }
+    }
   }
   double RU[NC], RV[NC], RW[NC];
   T vt[NC];
@@ -205,13 +215,15 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
 
 // ------------------------------------------------------------ 2D stage kernel
 // Loads row r of column gcol (ghost rows and columns by index map). With
-// WALLS (some boundary is reflective): xm, this lane is a ghost column behind
-// a reflective wall; xwall, some lane of the wavefront is (wave-uniform, so
-// unaffected blocks skip the sign rules). Problems without walls use the
-// kernel without this code, whose register allocation it would disturb.
+// WALLS (some boundary is reflective or fixed): xm, this lane is a ghost
+// column behind a reflective wall; xf, the fixed side whose state this ghost
+// lane holds (or -1); xwall, some lane of the wavefront is either
+// (wave-uniform, so unaffected blocks skip this code). Problems with neither
+// use the kernel without this code, whose register allocation it would
+// disturb.
 template <class Sys, bool WALLS, typename T>
 __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol, bool xwall,
-                                         bool xm, T (&U)[Sys::NC], T (&V)[Sys::NC],
+                                         bool xm, int xf, T (&U)[Sys::NC], T (&V)[Sys::NC],
                                          T (&W)[Sys::NC]) {
   const int gr = map_index(r, A.ny, A.bc[2], A.bc[3]);
   const int off = gr * A.nx + gcol;
@@ -221,29 +233,41 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol,
     V[c] = A.V[c * A.plane + off];
     W[c] = A.W[c * A.plane + off];
   }
-  if constexpr (Sys::kChar && WALLS) {
+  if constexpr (WALLS) {
+    auto fix = [&](int side) {
+#pragma unroll
+      for (int c = 0; c < Sys::NC; ++c) {
+        U[c] = T(A.gs[side][c]);
+        V[c] = T(0);
+        W[c] = T(0);
+      }
+    };
     if (xwall) {
       mirror_state<Sys, 0>(xm, U);
       mirror_normal_derivative<Sys, 0>(xm, V);
       mirror_state<Sys, 0>(xm, W);
+      if (xf >= 0) fix(xf);
     }
     if (mirrored(r, A.ny, A.bc[2], A.bc[3])) {
       mirror_state<Sys, 1>(true, U);
       mirror_state<Sys, 1>(true, V);
       mirror_normal_derivative<Sys, 1>(true, W);
     }
+    const int yf = fixed_side(r, A.ny, A.bc[2], A.bc[3]);
+    if (yf >= 0) fix(2 + yf);
   }
 }
 
-// VAR: kVarWalls (some boundary is reflective), kVarIface (interface basis);
-// each combination is its own instantiation, so the common one carries no
-// code of the others.
-constexpr int kVarWalls = 1, kVarIface = 2;
+// VAR: kVarWalls (some boundary is reflective or fixed), kVarIface (interface
+// basis), kVarSource (the gravity source of (euler2d-s)); each combination is
+// its own instantiation, so the common one carries no code of the others.
+constexpr int kVarWalls = 1, kVarIface = 2, kVarSource = 4;
 
 template <class Sys, typename T, int MODE, int VAR>
 __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   constexpr bool WALLS = (VAR & kVarWalls) != 0;
   constexpr bool IFACE = (VAR & kVarIface) != 0;
+  constexpr bool SOURCE = (VAR & kVarSource) != 0 && Sys::kChar && Sys::NC == 4;
   constexpr int NC = Sys::NC;
   if (MODE != kRhs && A.active && *A.active == 0) return;
   const Scheme& s = A.s;
@@ -252,9 +276,10 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   const int gcol = map_index(col, A.nx, A.bc[0], A.bc[1]);
   const bool out_col = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
   const bool xm = mirrored(col, A.nx, A.bc[0], A.bc[1]);
+  const int xf = fixed_side(col, A.nx, A.bc[0], A.bc[1]);
   const int col0 = blockIdx.x * kXOut - kHalo;   // the wavefront's first column
-  const bool xwall = (A.bc[0] == kBcReflective && col0 < 0) ||
-                     (A.bc[1] == kBcReflective && col0 + kWave > A.nx);
+  auto special = [](int b) { return b == kBcReflective || b == kBcDirichlet; };
+  const bool xwall = (special(A.bc[0]) && col0 < 0) || (special(A.bc[1]) && col0 + kWave > A.nx);
   const int y0 = blockIdx.y * A.rows;
   const int y1 = min(y0 + A.rows, A.ny);
   const double ax = A.alpha[0], ay = A.alpha[1];
@@ -278,12 +303,12 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   unsigned flag = 0;
 
   T Un[NC], Vn[NC], Wn[NC];
-  load_row<Sys, WALLS>(A, y0 - 2, gcol, xwall, xm, Un, Vn, Wn);
+  load_row<Sys, WALLS>(A, y0 - 2, gcol, xwall, xm, xf, Un, Vn, Wn);
   for (int r = y0 - 2; r < y1 + 2; ++r) {
     T Uc[NC], Vc[NC], Wc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) { Uc[c] = Un[c]; Vc[c] = Vn[c]; Wc[c] = Wn[c]; }
-    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, r + 1, gcol, xwall, xm, Un, Vn, Wn);  // prefetch
+    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, r + 1, gcol, xwall, xm, xf, Un, Vn, Wn);  // prefetch
     // RK base of this iteration's output row, loaded early to hide latency
     T Bu[NC], Bv[NC], Bw[NC];
     if (MODE >= kStage2 && r >= y0 + 2 && out_col) {
@@ -365,9 +390,18 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
           T Unew[NC];
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const double Lu = RU[c] - ((double)Gn[c] - (double)Fg[c]) * s.idy;
-            const double Lv = RV[c] - ((double)Xn[c] - (double)Fx[c]) * s.idy;
-            const double Lw = RW[c] - ((double)Tn[c] - (double)Ft[c]) * s.idy;
+            double Lu = RU[c] - ((double)Gn[c] - (double)Fg[c]) * s.idy;
+            double Lv = RV[c] - ((double)Xn[c] - (double)Fx[c]) * s.idy;
+            double Lw = RW[c] - ((double)Tn[c] - (double)Ft[c]) * s.idy;
+            if constexpr (SOURCE) {
+              // S(X) = g (0, 0, X_0, X_2) for X = u, v, w of the stage state
+              if (c >= 2) {
+                const int k = c == 2 ? 0 : 2;
+                Lu += A.gravity * (double)Ua[k];
+                Lv += A.gravity * (double)Va[k];
+                Lw += A.gravity * (double)Wa[k];
+              }
+            }
             const int idx = c * A.plane + o * A.nx + col;
             const double ub = MODE >= kStage2 ? (double)Bu[c] : 0.0;
             const double vb = MODE >= kStage2 ? (double)Bv[c] : 0.0;
@@ -552,7 +586,8 @@ __global__ void ws_init_kernel(StepScalars* sc) {
 // The ghost cells whose image is cell x of a line of n cells: slots 0..3 are
 // the virtual cells -2, -1, n, n+1; a cell is the image of at most two of
 // them (a transmissive edge cell of both ghosts of its side), listed in slot
-// order, each with whether the reflective sign rules apply.
+// order, each with whether the reflective sign rules apply. Fixed-state
+// ghosts have no image (their values do not depend on the state).
 struct GhostImages {
   int a, b;
   bool flip_a, flip_b;
@@ -561,7 +596,7 @@ __device__ __forceinline__ GhostImages ghost_images(int x, int n, int lo, int hi
   GhostImages g{-1, -1, false, false};
   for (int k = 0; k < 4; ++k) {
     const int v = k < 2 ? k - 2 : n + k - 2;
-    if (map_index(v, n, lo, hi) != x) continue;
+    if (fixed_side(v, n, lo, hi) >= 0 || map_index(v, n, lo, hi) != x) continue;
     if (g.a < 0) {
       g.a = k;
       g.flip_a = mirrored(v, n, lo, hi);
@@ -588,12 +623,14 @@ struct VjpArgs {
   T* ghost;               // [rows][4][3][NC] contributions of virtual cells -2, -1, n, n+1
   int n, rows, plane;
   int bc_lo, bc_hi;
+  double gs[2][4];        // fixed ghost states of the low and high side
   double h, ih;
   Scheme s;
 };
 
 template <class Sys, typename T, int D, int NF, int NA, bool WALLS>
 __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
+  // WALLS: some side of this direction is reflective or fixed
   constexpr int NC = Sys::NC;
   using Bar = typename BarOf<Sys, T>::type;
   const int lane = threadIdx.x;
@@ -620,6 +657,15 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     mirror_state<Sys, D>(m, U);
     mirror_normal_derivative<Sys, D>(m, Av);
     mirror_state<Sys, D>(m, Ov);
+    const int fs = fixed_side(v, A.n, A.bc_lo, A.bc_hi);
+    if (fs >= 0) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        U[c] = T(A.gs[fs][c]);
+        Av[c] = T(0);
+        Ov[c] = T(0);
+      }
+    }
   }
   // cotangents; zero at ghost cells (L and B are defined on interior cells)
   T aU[NC], aA[NC], bU[NC], bA[NC], bO[NC];
@@ -781,6 +827,7 @@ struct VjpYArgs {
   int nx, ny, rows, plane;
   int bc_lo, bc_hi;
   int bcx_lo, bcx_hi;     // boundaries of the x-pass, whose ghost columns are folded here
+  double gs[2][4];        // fixed ghost states of the low and high side (y)
   Scheme s;
 };
 
@@ -831,6 +878,15 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
         mirror_state<Sys, 1>(true, Uc);
         mirror_state<Sys, 1>(true, Vc);
         mirror_normal_derivative<Sys, 1>(true, Wc);
+      }
+      const int fs = fixed_side(r, A.ny, A.bc_lo, A.bc_hi);
+      if (fs >= 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          Uc[c] = T(A.gs[fs][c]);
+          Vc[c] = T(0);
+          Wc[c] = T(0);
+        }
       }
     }
     // interface (r-1)+1/2: L_j = -(F_{j+1/2} - F_{j-1/2}) / dy
@@ -998,7 +1054,8 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
 // terms aimed at ghost rows go into the ghost side buffer) and then the ghost
 // rows -2, -1, ny, ny+1, each into its image by the boundary's index map
 // (periodic: ny-2, ny-1, 0, 1; transmissive: 0, 0, ny-1, ny-1; reflective:
-// 1, 0, ny-1, ny-2 with the wall's sign rules). Images are always edge rows.
+// 1, 0, ny-1, ny-2 with the wall's sign rules; fixed states: none). Images
+// are always edge rows.
 // Strip k owns the virtual rows [-2 + k R, -2 + (k+1) R).
 template <typename T>
 __global__ __launch_bounds__(256) void vjp_y_fold_kernel(T* __restrict__ G0, T* __restrict__ G1,
@@ -1058,6 +1115,7 @@ __global__ __launch_bounds__(256) void vjp_y_fold_kernel(T* __restrict__ G0, T* 
 #pragma unroll
   for (int k = 0; k < 4; ++k) {   // ghost rows -2, -1, ny, ny+1
     const int v = k < 2 ? k - 2 : ny + k - 2;
+    if (fixed_side(v, ny, lo, hi) >= 0) continue;   // fixed states: no image
     const bool neg = mirrored(v, ny, lo, hi) && mirror_flips(1, f, c);
     G[(size_t)map_index(v, ny, lo, hi) * nx] += neg ? -gv[k] : gv[k];
   }
@@ -1084,8 +1142,30 @@ __global__ __launch_bounds__(256) void ghost_fold_kernel(T* __restrict__ G0, T* 
 #pragma unroll
   for (int k = 0; k < 4; ++k) {   // virtual cells -2, -1, n, n+1
     const int v = k < 2 ? k - 2 : n + k - 2;
+    if (fixed_side(v, n, lo, hi) >= 0) continue;    // fixed states: no image
     const bool neg = mirrored(v, n, lo, hi) && mirror_flips(0, f, c);
     G[map_index(v, n, lo, hi)] += neg ? -gv[k] : gv[k];
+  }
+}
+
+// Transpose of the gravity source (euler2d-s) of one stage:
+// G_f += S^T (c dt b_f) for the fields f = u, v, w, where S(X) = g (0, 0,
+// X_0, X_2): G_f[0] += g c dt b_f[2], G_f[2] += g c dt b_f[3].
+template <typename T>
+__global__ __launch_bounds__(256) void source_vjp_kernel(T* __restrict__ G0, T* __restrict__ G1,
+                                                         T* __restrict__ G2, const T* __restrict__ b0,
+                                                         const T* __restrict__ b1,
+                                                         const T* __restrict__ b2, double cb,
+                                                         const double* dt, double g, int plane) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= plane) return;
+  const T k = T(g * cb * *dt);
+  T* Gs[3] = {G0, G1, G2};
+  const T* bs[3] = {b0, b1, b2};
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    Gs[f][i] += k * bs[f][2 * plane + i];
+    Gs[f][2 * plane + i] += k * bs[f][3 * plane + i];
   }
 }
 
@@ -1126,11 +1206,25 @@ hweno_status validate(const hweno_problem* p) {
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return HWENO_EINVAL;
   for (int k = 0; k < 4; ++k) {
     if (p->bc[k] != HWENO_PERIODIC && p->bc[k] != HWENO_TRANSMISSIVE &&
-        p->bc[k] != HWENO_REFLECTIVE)
+        p->bc[k] != HWENO_REFLECTIVE && p->bc[k] != HWENO_DIRICHLET)
       return HWENO_EINVAL;
     // reflective walls are defined for the Euler equations only
     if (p->bc[k] == HWENO_REFLECTIVE && p->system != HWENO_EULER) return HWENO_EINVAL;
+    if (p->bc[k] == HWENO_DIRICHLET && (k < 2 || p->dim == 2)) {
+      const double* q = p->bc_state[k];
+      const int nc = p->system == HWENO_EULER ? p->dim + 2 : 1;
+      for (int c = 0; c < nc; ++c)
+        if (!std::isfinite(q[c])) return HWENO_EINVAL;
+      if (p->system == HWENO_EULER) {
+        double m2 = 0.0;
+        for (int c = 1; c < nc - 1; ++c) m2 += q[c] * q[c];
+        if (!(q[0] > 0.0) || !((p->gas_gamma - 1.0) * (q[nc - 1] - 0.5 * m2 / q[0]) > 0.0))
+          return HWENO_EINVAL;
+      }
+    }
   }
+  if (!std::isfinite(p->gravity)) return HWENO_EINVAL;
+  if (p->gravity != 0.0 && !(p->system == HWENO_EULER && p->dim == 2)) return HWENO_EINVAL;
   if ((p->bc[0] == HWENO_PERIODIC) != (p->bc[1] == HWENO_PERIODIC)) return HWENO_EINVAL;
   if (p->dim == 2 && (p->bc[2] == HWENO_PERIODIC) != (p->bc[3] == HWENO_PERIODIC))
     return HWENO_EINVAL;
@@ -1345,15 +1439,22 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
       }
     };
     bool walls = false;
-    for (int k = 0; k < 4; ++k) walls = walls || A.bc[k] == kBcReflective;
+    for (int k = 0; k < 4; ++k) walls = walls || A.bc[k] == kBcReflective || A.bc[k] == kBcDirichlet;
+    const int var = (walls ? kVarWalls : 0) | (Sys::kChar && A.iface ? kVarIface : 0) |
+                    (Sys::kChar && A.gravity != 0.0 ? kVarSource : 0);
     if constexpr (Sys::kChar) {
-      const int var = (walls ? kVarWalls : 0) | (A.iface ? kVarIface : 0);
       switch (var) {
         case 0: modes(std::integral_constant<int, 0>{}); break;
-        case kVarWalls: modes(std::integral_constant<int, kVarWalls>{}); break;
-        case kVarIface: modes(std::integral_constant<int, kVarIface>{}); break;
-        default: modes(std::integral_constant<int, kVarWalls | kVarIface>{}); break;
+        case 1: modes(std::integral_constant<int, 1>{}); break;
+        case 2: modes(std::integral_constant<int, 2>{}); break;
+        case 3: modes(std::integral_constant<int, 3>{}); break;
+        case 4: modes(std::integral_constant<int, 4>{}); break;
+        case 5: modes(std::integral_constant<int, 5>{}); break;
+        case 6: modes(std::integral_constant<int, 6>{}); break;
+        default: modes(std::integral_constant<int, 7>{}); break;
       }
+    } else if (walls) {
+      modes(std::integral_constant<int, kVarWalls>{});
     } else {
       modes(std::integral_constant<int, 0>{});
     }
@@ -1371,6 +1472,9 @@ StageArgs<T> base_args(const hweno_problem* p) {
   A.plane = p->nx * p->ny;
   for (int k = 0; k < 4; ++k) A.bc[k] = p->bc[k];
   A.iface = p->char_basis == HWENO_BASIS_INTERFACE;
+  for (int k = 0; k < 4; ++k)
+    for (int c = 0; c < 4; ++c) A.gs[k][c] = p->bc_state[k][c];
+  A.gravity = p->system == HWENO_EULER && p->dim == 2 ? p->gravity : 0.0;
   A.s = make_scheme(p);
   return A;
 }
@@ -1431,11 +1535,16 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.plane = plane;
     A.bc_lo = p->bc[0];
     A.bc_hi = p->bc[1];
+    for (int c = 0; c < 4; ++c) {
+      A.gs[0][c] = p->bc_state[0][c];
+      A.gs[1][c] = p->bc_state[1][c];
+    }
     A.h = sc.dx;
     A.ih = sc.idx;
     A.s = sc;
     dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
-    const bool xwalls = p->bc[0] == HWENO_REFLECTIVE || p->bc[1] == HWENO_REFLECTIVE;
+    auto special = [](int b) { return b == HWENO_REFLECTIVE || b == HWENO_DIRICHLET; };
+    const bool xwalls = special(p->bc[0]) || special(p->bc[1]);
     auto go = [&](auto walls) {
       constexpr bool W = decltype(walls)::value;
       if (cot.na == 1)
@@ -1443,20 +1552,24 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
       else
         vjp_row_kernel<Sys, T, 0, DIM + 1, 3, W><<<grid, kWave, 0, st>>>(A, sy);
     };
-    if constexpr (Sys::kChar) {
-      if (xwalls)
-        go(std::true_type{});
-      else
-        go(std::false_type{});
-    } else {
+    if (xwalls)
+      go(std::true_type{});
+    else
       go(std::false_type{});
-    }
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     if constexpr (DIM == 1) {   // in 2D the y-pass folds these
       const int tot = ny * g.nf * NC;
       ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
                                                              nx, ny, plane, NC, g.nf,
                                                              p->bc[0], p->bc[1]);
+      if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    }
+  }
+  if constexpr (DIM == 2) {
+    if (Sys::kChar && NC == 4 && p->gravity != 0.0) {
+      source_vjp_kernel<T><<<(plane + 255) / 256, 256, 0, st>>>(
+          out[0], out[1], out[2], (const T*)cot.b[0], (const T*)cot.b[1], (const T*)cot.b[2], cot.cb,
+          dt, p->gravity, plane);
       if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     }
   }
@@ -1486,11 +1599,15 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.bc_hi = p->bc[3];
     A.bcx_lo = p->bc[0];
     A.bcx_hi = p->bc[1];
+    for (int c = 0; c < 4; ++c) {
+      A.gs[0][c] = p->bc_state[2][c];
+      A.gs[1][c] = p->bc_state[3][c];
+    }
     A.s = sc;
     // strips of at least kMinStripRows rows (the halo buffer is sized for
     // that); warm-up: four rows of loads
     bool walls = false;
-    for (int k = 0; k < 4; ++k) walls = walls || p->bc[k] == HWENO_REFLECTIVE;
+    for (int k = 0; k < 4; ++k) walls = walls || p->bc[k] == HWENO_REFLECTIVE || p->bc[k] == HWENO_DIRICHLET;
     int nstrips = 0;
     auto go = [&](auto kernel, auto tag) {
       int per_cu = 0, cus = 0;
@@ -1501,14 +1618,10 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
       dim3 grid((nx + kWave - 1) / kWave, nstrips);
       kernel<<<grid, kWave, 0, st>>>(A, sy);
     };
-    if constexpr (Sys::kChar) {
-      if (walls)
-        go(vjp_y_kernel<Sys, T, true>, std::integral_constant<int, 20>{});
-      else
-        go(vjp_y_kernel<Sys, T, false>, std::integral_constant<int, 4>{});
-    } else {
+    if (walls)
+      go(vjp_y_kernel<Sys, T, true>, std::integral_constant<int, 20>{});
+    else
       go(vjp_y_kernel<Sys, T, false>, std::integral_constant<int, 4>{});
-    }
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     const long tot = 3L * NC * nx * nstrips;
     vjp_y_fold_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(

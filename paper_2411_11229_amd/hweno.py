@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, 'libhweno.so')
 
 SYSTEMS = {'advection': 0, 'burgers': 1, 'euler': 2}
-BCS = {'periodic': 0, 'transmissive': 1, 'reflective': 2}
+BCS = {'periodic': 0, 'transmissive': 1, 'reflective': 2, 'dirichlet': 3}
 PRECISIONS = {'f64': 0, 'f32': 1}
 BASES = {'cell': 0, 'interface': 1}
 DT_RULES = {'production': 0, 'accuracy': 1, 'fixed': 2}
@@ -39,7 +39,8 @@ class _CProblem(ctypes.Structure):
                 ('gas_gamma', ctypes.c_double), ('gamma0', ctypes.c_double),
                 ('d0', ctypes.c_double), ('eps', ctypes.c_double),
                 ('bc', ctypes.c_int32 * 4), ('precision', ctypes.c_int32),
-                ('char_basis', ctypes.c_int32)]
+                ('char_basis', ctypes.c_int32), ('bc_state', (ctypes.c_double * 4) * 4),
+                ('gravity', ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -102,6 +103,8 @@ class Problem:
     bc: tuple = ('periodic',) * 4
     precision: str = 'f64'
     basis: str = 'cell'               # characteristic basis: 'cell' | 'interface'
+    bc_state: tuple = (None, None, None, None)   # conserved states of 'dirichlet' sides
+    gravity: float = 0.0              # g of the (euler2d-s) source, 2D Euler only
 
     def __post_init__(self):
         if self.gamma0 is None:
@@ -130,6 +133,11 @@ class Problem:
             p.bc[k] = BCS[self.bc[k]]
         p.precision = PRECISIONS[self.precision]
         p.char_basis = BASES[self.basis]
+        for k, st in enumerate(self.bc_state):
+            if st is not None:
+                for c, v in enumerate(st):
+                    p.bc_state[k][c] = float(v)
+        p.gravity = float(self.gravity)
         return p
 
 

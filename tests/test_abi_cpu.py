@@ -80,6 +80,21 @@ def test_reflective_walls_accepted_for_euler(lib, bc):
     assert _ws_bytes(lib, _prob(dim=1, ny=1, bc=bc))[0] == 0
 
 
+def test_fixed_states_and_gravity_validated(lib):
+    good = (1.0, 0.2, -0.1, 2.5)
+    bc = ('dirichlet', 'transmissive', 'reflective', 'dirichlet')
+    assert _ws_bytes(lib, _prob(bc=bc, bc_state=(good, None, None, good), gravity=1.0))[0] == 0
+    # non-physical or non-finite fixed state, gravity outside 2D Euler
+    for bad in ((-1.0, 0.0, 0.0, 2.5), (1.0, 3.0, 0.0, 1.0), (1.0, float('nan'), 0.0, 2.5)):
+        assert _ws_bytes(lib, _prob(bc=bc, bc_state=(bad, None, None, good)))[0] == -1
+    assert _ws_bytes(lib, _prob(dim=1, ny=1, gravity=1.0))[0] == -1
+    assert _ws_bytes(lib, _prob(system='burgers', gravity=1.0))[0] == -1
+    assert _ws_bytes(lib, _prob(gravity=float('inf')))[0] == -1
+    # scalar laws take fixed states too (first component)
+    assert _ws_bytes(lib, _prob(system='burgers', bc=('dirichlet', 'dirichlet', 'periodic', 'periodic'),
+                                bc_state=((0.3,), (0.1,), None, None)))[0] == 0
+
+
 def test_interface_basis_accepted(lib):
     assert _ws_bytes(lib, _prob(basis='interface'))[0] == 0
     assert _ws_bytes(lib, _prob(system='burgers', basis='interface'))[0] == 0

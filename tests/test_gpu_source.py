@@ -1,0 +1,223 @@
+"""Fixed-state (Dirichlet) boundaries and the gravity source of (euler2d-s)
+on the HIP path against the FP64 oracle (Example 4.11, Rayleigh-Taylor),
+forward and adjoint, with the tolerances of the other parity tests."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hweno as O
+from paper_2411_11229_amd import workloads as WL
+
+from test_gpu_parity import (RTOL64, check_run, dev, f32_bounds, host, oprob, oracle_sensitivity,
+                             solver)
+from test_gpu_adjoint import _gpu_grad, _oracle_grad, frozen_map, state
+
+pytestmark = pytest.mark.gpu
+
+G53 = 5.0 / 3.0
+
+
+def cons(r, u, v, p, g=1.4):
+    return (r, r * u, r * v, p / (g - 1.0) + 0.5 * r * (u * u + v * v))
+
+
+def dirichlet(w, bc, states):
+    import dataclasses
+    return dataclasses.replace(w, bc=bc, bc_state=states)
+
+
+def cases():
+    q = WL.euler2d_quadrants(121, seed=4501, ny=37)
+    s = WL.euler2d_smooth(64, seed=3501, ny=50)
+    e1 = WL.euler1d_riemann_sine(130, seed=2501)
+    b1 = WL.random_smooth_1d(70, 'burgers', seed=91)
+    b2 = WL.paper_burgers2d(40)
+    return [
+        ('rt-16x64', WL.rayleigh_taylor(16)),
+        ('rt-60x240', WL.rayleigh_taylor(60)),
+        ('quadrants-121x37-dirichlet-x', dirichlet(q, ('dirichlet', 'dirichlet', 'transmissive', 'reflective'),
+                                                   (cons(1.0, 0.3, -0.2, 2.0), cons(0.5, -0.1, 0.4, 1.5),
+                                                    None, None))),
+        ('smooth-64x50-gravity-periodic', WL.Workload(**{**s.__dict__, 'gravity': 0.7})),
+        ('euler1d-130-dirichlet', dirichlet(e1, ('dirichlet', 'dirichlet', 'periodic', 'periodic'),
+                                            ((1.2, 0.5, 3.0), (0.8, -0.3, 2.5), None, None))),
+        ('burgers1d-70-dirichlet', dirichlet(b1, ('dirichlet', 'transmissive', 'periodic', 'periodic'),
+                                             ((0.4,), None, None, None))),
+        ('burgers2d-40-dirichlet', dirichlet(b2, ('periodic', 'periodic', 'dirichlet', 'dirichlet'),
+                                             (None, None, (0.2,), (0.9,)))),
+    ]
+
+
+def _scale(w, k, r):
+    scale = np.max(np.abs(r))
+    if k >= 3:
+        ax, h, D = (-1, w.dx, w.V) if k == 3 else (-2, w.dy, w.W)
+        scale = max(scale, np.max(np.abs(np.diff(w.U, axis=ax))) / h, np.max(np.abs(D)))
+    return scale
+
+
+@pytest.mark.parametrize("name,w", cases(), ids=[c[0] for c in cases()])
+def test_source_and_fixed_states_rhs_matches_oracle_f64(name, w):
+    print(f'case {name}', flush=True)
+    s = solver(w)
+    p = oprob(w)
+    alpha = O.max_speed(p, w.U)
+    ref = O.rhs(p, w.U, w.V, w.W, alpha)
+    two = w.dim == 2
+    got = s.rhs(dev(w.U), dev(w.V), dev(w.W) if two else None, dev(np.array(alpha)))
+    for k, (g, r) in enumerate(zip(got, ref)):
+        if r is None:
+            continue
+        e = np.max(np.abs(host(g) - r)) / _scale(w, k, r)
+        print(f'  output {k}: rel err {e:.3e}')
+        assert e <= RTOL64, f'{name} output {k}: {e:.3e}'
+
+
+def test_rayleigh_taylor_rhs_f32():
+    w = WL.rayleigh_taylor(24)
+    w.U = w.U.astype(np.float32).astype(np.float64)
+    w.V = w.V.astype(np.float32).astype(np.float64)
+    w.W = w.W.astype(np.float32).astype(np.float64)
+    s = solver(w, precision='f32')
+    p = oprob(w)
+    alpha = O.max_speed(p, w.U)
+    f32 = lambda a: dev(a, torch.float32)
+    got = s.rhs(f32(w.U), f32(w.V), f32(w.W), dev(np.array(alpha)))
+    ref = O.rhs(p, w.U, w.V, w.W, alpha)
+    tol = f32_bounds(w, alpha)
+    # the source adds |g X| rounded once in float to each residual
+    src = [np.max(np.abs(X)) * 1.0 * 2.0 ** -23 for X in (w.U, w.V, w.W)]
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = np.max(np.abs(host(g) - r))
+        bound = tol[k] + (src[k] if k < 3 else 0.0)
+        print(f'  output {k}: abs err {err:.3e}  bound {bound:.3e}')
+        assert err <= bound
+
+
+@pytest.mark.parametrize("name,w", [cases()[k] for k in (1, 2, 4)], ids=[cases()[k][0] for k in (1, 2, 4)])
+def test_source_and_fixed_states_step_matches_oracle_f64(name, w):
+    s = solver(w)
+    p = oprob(w)
+    two = w.dim == 2
+    U, V = dev(w.U), dev(w.V)
+    W = dev(w.W) if two else None
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dt = torch.zeros(1, dtype=torch.float64, device='cuda')
+    s.step(U, V, W, t, 1e9, dt_used=dt)
+    alpha = O.max_speed(p, w.U)
+    dto = O.time_step(p, alpha)
+    assert float(dt.item()) == pytest.approx(dto, rel=1e-14)
+    Uo, Vo, Wo, _ = O.step(p, w.U, w.V, w.W, dto, (alpha, None, None))
+    for k, (g, r) in enumerate(zip((U, V, W), (Uo, Vo, Wo))):
+        if r is None:
+            continue
+        e = np.max(np.abs(host(g) - r)) / np.max(np.abs(r))
+        print(f'  field {k}: rel err {e:.3e}')
+        assert e <= RTOL64, f'{name} field {k}: {e:.3e}'
+
+
+def test_rayleigh_taylor_run_matches_oracle_and_stays_symmetric():
+    w = WL.rayleigh_taylor(32)
+    s = solver(w)
+    U, V, W = dev(w.U), dev(w.V), dev(w.W)
+    n, t, dts = s.run(U, V, W, t_end=1e9, max_steps=25)
+    p = oprob(w)
+    run = lambda a, b, c: O.run(p, a, b, c, 1e9, max_steps=25)[:3]
+    base, worst = oracle_sensitivity(p, w, run)
+    check_run(w, (U, V, W), base, worst, 'rayleigh-taylor-32x128')
+    sign = torch.tensor([1.0, -1.0, 1.0, 1.0], dtype=torch.float64, device='cuda')[:, None, None]
+    for X, sg in ((U, sign), (W, sign), (V, -sign)):
+        asym = float((X - sg * X.flip(-1)).abs().max() / X.abs().max())
+        print(f'  mirror asymmetry {asym:.2e}')
+        assert asym <= 1e-12
+    s.health()
+
+
+ADJ = [('rt-12x48', lambda: WL.rayleigh_taylor(12)),
+       ('quadrants-dirichlet', lambda: dirichlet(WL.euler2d_quadrants(70, seed=4502, ny=40),
+                                                 ('dirichlet', 'transmissive', 'reflective', 'dirichlet'),
+                                                 (cons(1.0, 0.3, -0.2, 2.0), None, None,
+                                                  cons(0.7, 0.1, 0.2, 1.2)))),
+       ('euler1d-dirichlet', lambda: dirichlet(WL.euler1d_riemann_sine(90, seed=2502),
+                                               ('transmissive', 'dirichlet', 'periodic', 'periodic'),
+                                               (None, (0.8, -0.3, 2.5), None, None)))]
+
+
+@pytest.mark.parametrize("name,mk", ADJ, ids=[a[0] for a in ADJ])
+def test_adjoint_step_with_source_and_fixed_states(name, mk):
+    """One adjoint step against the oracle's reverse mode of the same frozen
+    step (the dt and stage alphas the GPU recorded), element by element."""
+    w = mk()
+    s = solver(w)
+    X = state(w)
+    two = len(X) == 3
+    Y = [x.clone() for x in X]
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dt = torch.zeros(1, dtype=torch.float64, device='cuda')
+    rec = torch.zeros(6, dtype=torch.float64, device='cuda')
+    s.step(Y[0], Y[1], Y[2] if two else None, t, 1e9, dt_used=dt, alpha_rec=rec)
+    g = torch.Generator(device='cuda').manual_seed(9)
+    lam = [torch.randn(x.shape, dtype=x.dtype, device='cuda', generator=g) for x in X]
+    out = [torch.empty_like(x) for x in X]
+    s.adjoint_step(X[0], X[1], X[2] if two else None, dt, rec, lam, out)
+    # oracle: d<lam, step(X)>/dX by torch-CPU reverse mode
+    p = oprob(w)
+    r = host(rec).reshape(3, 2)
+    alphas = tuple((float(a[0]), float(a[1])) for a in r)
+    Xo = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (w.U, w.V, w.W) if a is not None]
+    Yo = O.step(p, Xo[0], Xo[1], Xo[2] if two else None, float(dt.item()), alphas)[:len(Xo)]
+    J = sum((torch.tensor(host(l)) * y).sum() for l, y in zip(lam, Yo))
+    J.backward()
+    for k, (a, x) in enumerate(zip(out, Xo)):
+        ref = x.grad.numpy()
+        err = np.max(np.abs(host(a) - ref)) / np.max(np.abs(ref))
+        print(f'  field {k}: rel err {err:.3e}')
+        assert err <= 1e-9, f'{name} field {k}: {err:.3e}'
+    if name.startswith('rt'):
+        # and along a random direction against extrapolated differences
+        delta = [torch.randn(x.shape, dtype=x.dtype, device='cuda', generator=g) for x in X]
+        adj = sum(float((o * d).sum()) for o, d in zip(out, delta))
+
+        def D(e):
+            Xp = frozen_map(s, [x + e * d for x, d in zip(X, delta)], dt, rec)
+            Xm = frozen_map(s, [x - e * d for x, d in zip(X, delta)], dt, rec)
+            return sum(float((l * (p_ - m)).sum()) for l, p_, m in zip(lam, Xp, Xm)) / (2 * e)
+        fd = (4 * D(1e-7) - D(2e-7)) / 3
+        print(f'  adjoint {adj:.12e}  fd {fd:.12e}')
+        assert adj == pytest.approx(fd, rel=1e-6)
+
+
+def test_rayleigh_taylor_rollout_gradient_matches_oracle():
+    w = WL.rayleigh_taylor(8)
+    rng = np.random.default_rng(13)
+    target = w.U + 0.05 * rng.standard_normal(w.U.shape)
+    go, Jo = _oracle_grad(w, 4, target)
+    gg, Jg = _gpu_grad(w, 4, target, every=2)
+    assert Jg == pytest.approx(Jo, rel=1e-10)
+    for k, (a, b) in enumerate(zip(gg, go)):
+        err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+        print(f'  field {k}: rel err {err:.3e}')
+        assert err <= 1e-8
+
+
+def test_rayleigh_taylor_to_final_time():
+    """Example 4.11 at 60 x 240 to t = 1.95 (about 3300 steps): the run stays
+    admissible, the heavy fluid falls and the light fluid rises (densities
+    below / above y = 1/2 leave their initial values). The instability
+    amplifies round-off asymmetry (1e-14 after 25 steps) to a few percent by
+    t = 1.95, so the mirror symmetry is printed, not asserted, here."""
+    import time
+    w = WL.rayleigh_taylor(60)
+    s = solver(w)
+    U, V, W = dev(w.U), dev(w.V), dev(w.W)
+    t0 = time.perf_counter()
+    n, t, dts = s.run(U, V, W, t_end=w.t_end)
+    torch.cuda.synchronize()
+    print(f'  {n} steps to t = {t} in {time.perf_counter() - t0:.2f} s')
+    assert t == pytest.approx(w.t_end, abs=1e-14)
+    s.health()
+    sign = torch.tensor([1.0, -1.0, 1.0, 1.0], dtype=torch.float64, device='cuda')[:, None, None]
+    asym = float((U - sign * U.flip(-1)).abs().max() / U.abs().max())
+    print(f'  mirror asymmetry {asym:.2e}')
+    assert float(U[0, : w.ny // 2].min()) < 1.9
+    assert float(U[0, w.ny // 2:].max()) > 1.1
