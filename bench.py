@@ -287,6 +287,33 @@ def rayleigh_taylor_times():
     return out
 
 
+def double_mach_time(nx=1600):
+    """Example 4.7 at nx x nx/4 to t = 0.2, FP64 (five start-up steps at CFL
+    0.1, then 0.6): wall time with inputs resident."""
+    import torch
+    from paper_2411_11229_amd import hweno, workloads
+    w = workloads.double_mach(nx)
+    s = hweno.Solver(hweno.Problem(**w.problem_kwargs()))
+    d = lambda a: torch.tensor(a, dtype=torch.float64, device='cuda')
+    U, V, W = d(w.U), d(w.V), d(w.W)
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    for _ in range(5):
+        s.step(U, V, W, t, w.t_end, cfl=0.1)
+        n += 1
+    while float(t.item()) < w.t_end and n < 100000:
+        for _ in range(64):
+            s.step(U, V, W, t, w.t_end)
+        n += 64
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.health()
+    return dict(cells=f'{nx}x{nx // 4}', t=float(t.item()), wall_s=wall, steps_upper_bound=n,
+                rho_max=float(U[0].max()), rho_min=float(U[0].min()))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument('--gpus', type=int, default=1)
@@ -301,6 +328,8 @@ def main():
     ap.add_argument('--probe', choices=['copy'], help='run a calibration probe instead')
     ap.add_argument('--basis-robustness', action='store_true',
                     help='compare the cell and interface characteristic bases instead')
+    ap.add_argument('--double-mach', action='store_true',
+                    help='time the double Mach reflection example at 1600x400 instead')
     ap.add_argument('--rayleigh-taylor', action='store_true',
                     help='time the Rayleigh-Taylor example at the paper\'s meshes instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
@@ -324,6 +353,9 @@ def main():
         return
     if args.basis_robustness:
         print(json.dumps({'basis_robustness': basis_robustness()}))
+        return
+    if args.double_mach:
+        print(json.dumps({'double_mach': double_mach_time()}))
         return
     if args.rayleigh_taylor:
         print(json.dumps({'rayleigh_taylor': rayleigh_taylor_times()}))

@@ -67,11 +67,29 @@ typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_s
  *                 along the wall follows the state. HWENO_EULER only;
  *   dirichlet     a fixed state (the top and bottom boundaries of Example
  *                 4.11): both ghost cells hold bc_state[side] (conserved
- *                 variables), the derivatives v, w are 0 there.
+ *                 variables), the derivatives v, w are 0 there;
+ *   split         (y sides of 2D Euler only) a rule that changes along x and
+ *                 in time, as on the bottom and top of Example 4.7: see
+ *                 hweno_split. Only hweno_rhs (at t = 0) and hweno_step
+ *                 accept it; hweno_step_frozen and hweno_adjoint_step return
+ *                 HWENO_EUNSUPPORTED.
  * The two ends of an axis are independent except for periodic. */
 typedef enum {
-  HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2, HWENO_DIRICHLET = 3
+  HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2, HWENO_DIRICHLET = 3,
+  HWENO_SPLIT = 4
 } hweno_bc;
+
+/* A split y side: a ghost cell at (x, y) (cell centres, the domain's
+ * lower-left corner at the origin, so x = (i + 1/2) dx) follows kind[0] if
+ * x < x0 + slope * y + speed * t, else kind[1]; each kind is
+ * HWENO_TRANSMISSIVE, HWENO_REFLECTIVE or HWENO_DIRICHLET (with state[k],
+ * conserved variables). t is the stage time: t^n, t^n + dt, t^n + dt/2 for
+ * the three SSP-RK3 stages of hweno_step. */
+typedef struct {
+  double x0, slope, speed;
+  int32_t kind[2];
+  double state[2][4];
+} hweno_split;
 typedef enum { HWENO_F64 = 0, HWENO_F32 = 1 } hweno_precision;
 /* Characteristic basis of the HWENO interpolation for the Euler systems
  * (remark on systems in section 2, local characteristic decomposition):
@@ -118,6 +136,7 @@ typedef struct {
                         /* x_hi, y_lo, y_hi), first ncomp entries; finite, and    */
                         /* rho, P > 0 for Euler                                   */
   double gravity;       /* g of (euler2d-s); 0 unless system == EULER, dim == 2   */
+  hweno_split split[2]; /* y_lo, y_hi rules where bc[2] / bc[3] == HWENO_SPLIT    */
 } hweno_problem;
 
 /* Human-readable name of a status code (static string). */
@@ -143,8 +162,10 @@ hweno_status hweno_max_wavespeed(const hweno_problem* prob, const void* u, doubl
  * Lu, Lv, Lw <- L^1, L^2, L^3 of (odeH)/(ode2H) at the state (u, v, w) with
  * the given alphas (device double[2]); vtilde, wtilde <- the modified
  * derivatives of (limiter) in x and y. For systems the interpolation and
- * the limiter run in local characteristic variables of the cell centre.
- * Outputs must not alias inputs. In 1D, w, Lw and wtilde are NULL.
+ * the limiter run in local characteristic variables of the cell centre (or
+ * of the faces, see hweno_char_basis). Split sides are taken at t = 0. With
+ * `gravity` the source S of (euler2d-s) is included. Outputs must not alias
+ * inputs. In 1D, w, Lw and wtilde are NULL.
  */
 hweno_status hweno_rhs(const hweno_problem* prob, const void* u, const void* v, const void* w,
                        const double* alpha, void* Lu, void* Lv, void* Lw,
@@ -190,6 +211,7 @@ hweno_status hweno_step_profiled(const hweno_problem* prob, void* u, void* v, vo
  * clipping, no time update. The new state goes to (u_out, v_out, w_out) if
  * u_out is not NULL (then (u, v, w) are left unchanged and the outputs must
  * not overlap any input), else in place. `stages` as in hweno_step.
+ * HWENO_EUNSUPPORTED for split sides (the step carries no time).
  */
 hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void* w,
                                void* u_out, void* v_out, void* w_out, const double* dt,
@@ -213,7 +235,7 @@ hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void
  * |beta0 - beta_k| the derivative of |.| is taken as sign(0) = 0. Output
  * buffers must not alias any input. The result is deterministic: every sum
  * is formed in a fixed order, without atomics. Returns HWENO_EUNSUPPORTED
- * for the Euler systems with the interface basis.
+ * for the Euler systems with the interface basis and for split sides.
  */
 hweno_status hweno_adjoint_step(const hweno_problem* prob, const void* u_n, const void* v_n,
                                 const void* w_n, const void* stages, const double* dt,

@@ -37,6 +37,9 @@ notes of the repository):
     v~ keeps the cell basis.
   * Dirichlet boundary ('dirichlet', the fixed top and bottom states of
     Example 4.11): both ghost cells hold the given state, the derivatives 0.
+  * Split y-side ('split', Example 4.7's bottom and top): the rule of a ghost
+    cell changes at x = x0 + slope y + speed t, with the stage times
+    t, t + dt, t + dt/2 of SSP-RK3.
   * Source term (euler2d-s): S(u) added to L^1, S(v) and S(w) to the
     derivative equations (S is linear in u).
   * Reflective boundary (Euler only): mirror cells with the sign rules of
@@ -76,10 +79,12 @@ class Problem:
     basis: str = 'cell'             # characteristic basis: 'cell' | 'interface'
     bc_state: tuple = (None, None, None, None)   # conserved ghost state of 'dirichlet' sides
     gravity: float = 0.0            # g of the source term (euler2d-s), 2D Euler only
+    split: tuple = (None, None)     # Split rules of 'split' y-sides (y_lo, y_hi)
 
     def __post_init__(self):
         if self.gamma0 is None:
             self.gamma0 = 0.95 if self.dim == 1 else 0.99
+        self.split = tuple(Split(**sp) if isinstance(sp, dict) else sp for sp in self.split)
 
     @property
     def linear_gamma(self):
@@ -350,6 +355,63 @@ def pad(a, bc_lo, bc_hi, axis=-1, sign=None, fixed=(None, None)):
     return out * xp.const(fac, a)
 
 
+@dataclass
+class Split:
+    """A y-side whose rule changes along x and in time (Example 4.7's bottom
+    and top): ghost cell (x, y) at time t follows rule kinds[0] where
+    x < x0 + slope y + speed t, else kinds[1]; a 'dirichlet' kind holds
+    states[k] (conserved), with zero derivatives. Coordinates: cell centres
+    with the domain's lower-left corner at (0, 0)."""
+    x0: float
+    slope: float
+    speed: float
+    kinds: tuple
+    states: tuple = (None, None)
+
+
+def pad_lines(a, lo, hi, sign, fixed, deriv=False, xc=None, yg=None, t=0.0):
+    """``pad`` along the last axis where an end may be a ``Split`` (y-sides
+    only, arrays transposed to [comp, x, y]): each split end is padded under
+    both of its kinds and every ghost cell takes the kind its position
+    selects. deriv: ``a`` is a derivative field (zero in fixed-state
+    ghosts); xc: cell-centre x; yg: the ghost-row centres y (low pair, high
+    pair) in padded order; t: the stage time."""
+    xp = _array.ns(a)
+    plain = lambda e: 'transmissive' if isinstance(e, Split) else e
+    base = pad(a, plain(lo), plain(hi), sign=sign, fixed=fixed)
+    if not isinstance(lo, Split) and not isinstance(hi, Split):
+        return base
+    n = a.shape[-1]
+    npad = n + 2 * NG
+    out = base
+    for end, sp in ((0, lo), (1, hi)):
+        if not isinstance(sp, Split):
+            continue
+        cols = [0, 1] if end == 0 else [n + NG, n + NG + 1]
+        ys = yg[:2] if end == 0 else yg[2:]
+        pads = []
+        for k in range(2):
+            kind = sp.kinds[k]
+            st = None
+            if kind == 'dirichlet':
+                st = [0.0] * a.shape[0] if deriv else sp.states[k]
+            ends = [plain(lo), plain(hi)]
+            ends[end] = kind
+            fx = list(fixed)
+            fx[end] = st
+            pads.append(pad(a, ends[0], ends[1], sign=sign, fixed=tuple(fx)))
+        m = np.zeros((len(xc), npad))
+        own = np.zeros((len(xc), npad))
+        for j, y in zip(cols, ys):
+            m[:, j] = (np.asarray(xc) < sp.x0 + sp.slope * y + sp.speed * t).astype(float)
+            own[:, j] = 1.0
+        shape = (1, len(xc), npad)
+        m, own = m.reshape(shape), own.reshape(shape)
+        out = (out * xp.const(1.0 - own, a) + pads[0] * xp.const(own * m, a)
+               + pads[1] * xp.const(own * (1.0 - m), a))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Section 2.1: HWENO interpolation on one cell (scalar data, vectorised)
 # ----------------------------------------------------------------------------
@@ -463,21 +525,23 @@ def lax_friedrichs(fm, fp, um, up, alpha):
 # One directional sweep: Steps 1-3 of section 2 (and Steps 1/2 of section 3)
 # ----------------------------------------------------------------------------
 def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis='cell',
-          state=(None, None)):
+          state=(None, None), geo=None):
     """HWENO-I procedure along the last axis for direction ``d``.
 
     U: state; A: derivative along the sweep (v for x, w for y); B: the other
     derivative (w for x, v for y) or None in 1D. Returns the residual
     contributions -(F_{i+1/2} - F_{i-1/2})/h of the three equations
     (u-equation, A-equation, B-equation via the mixed flux) and the modified
-    derivative A~ at the interior cells.
+    derivative A~ at the interior cells. ``geo`` (y-sweep with split sides):
+    dict(xc=..., yg=..., t=...) for ``pad_lines``.
     """
     xp = _array.ns(U)
     n = U.shape[-1]
     sU, sA, sB = reflect_signs(sys, d)
     zero = [0.0] * U.shape[0]
-    Up = pad(U, bc_lo, bc_hi, sign=sU, fixed=state)
-    Ap = pad(A, bc_lo, bc_hi, sign=sA, fixed=(zero, zero))
+    geo = geo or {}
+    Up = pad_lines(U, bc_lo, bc_hi, sU, state, False, **geo)
+    Ap = pad_lines(A, bc_lo, bc_hi, sA, (zero, zero), True, **geo)
     # HWENO on cells -1..n (padded 1..n+2): interfaces -1/2..n-1/2 need them
     m, c, p = (slice(0, n + 2), slice(1, n + 3), slice(2, n + 4))
     Um, U0, Upl = Up[..., m], Up[..., c], Up[..., p]
@@ -523,7 +587,7 @@ def sweep(sys, d, U, A, B, h, alpha, bc_lo, bc_hi, lin_gamma, lin_d, eps, basis=
     RA = -(Hh[..., 1:] - Hh[..., :-1]) / h
     RB = None
     if B is not None:
-        Bp = pad(B, bc_lo, bc_hi, sign=sB, fixed=(zero, zero))
+        Bp = pad_lines(B, bc_lo, bc_hi, sB, (zero, zero), True, **geo)
         e = sys.jac_apply(Up, Bp, d)
         Eh = mixed_flux(e[..., q[0]], e[..., q[1]], e[..., q[2]], e[..., q[3]])
         RB = -(Eh[..., 1:] - Eh[..., :-1]) / h
@@ -541,10 +605,11 @@ def max_speed(prob, U):
     return (ax, ay)
 
 
-def rhs(prob, U, V, W=None, alpha=None):
+def rhs(prob, U, V, W=None, alpha=None, t=0.0):
     """L^1, L^2 (, L^3) of (odeH)/(ode2H) and the modified derivatives
-    v~ (, w~) of (limiter), for one stage state. Returns (L1, L2, L3, vt, wt);
-    L3, wt are None in 1D."""
+    v~ (, w~) of (limiter), for one stage state at time t (which only
+    time-dependent boundaries see). Returns (L1, L2, L3, vt, wt); L3, wt are
+    None in 1D."""
     sys = make_system(prob)
     if alpha is None:
         alpha = max_speed(prob, U)
@@ -556,13 +621,21 @@ def rhs(prob, U, V, W=None, alpha=None):
                               (st[0], st[1]))
         return L1, L2, None, vt, None
     xp = _array.ns(U)
+    time = t
     # Step 1: x-direction on (u, v); mixed flux eta = f'(u) w
     Lx1, Lx2, Lx3, vt = sweep(sys, 0, U, V, W, prob.dx, alpha[0], bx0, bx1, g, dl, eps, bs,
                               (st[0], st[1]))
     # Step 2: y-direction on (u, w); mixed flux xi = g'(u) v
     t = lambda a: xp.moveaxis(a, -1, -2)
+    geo = None
+    if prob.split[0] is not None or prob.split[1] is not None:
+        by0 = prob.split[0] if by0 == 'split' else by0
+        by1 = prob.split[1] if by1 == 'split' else by1
+        hy = prob.dy
+        geo = dict(xc=(np.arange(prob.nx) + 0.5) * prob.dx,
+                   yg=[-1.5 * hy, -0.5 * hy, (prob.ny + 0.5) * hy, (prob.ny + 1.5) * hy], t=time)
     Ly1, Ly3, Ly2, wt = sweep(sys, 1, t(U), t(W), t(V), prob.dy, alpha[1], by0, by1, g, dl, eps, bs,
-                              (st[2], st[3]))
+                              (st[2], st[3]), geo)
     # Step 4
     L1, L2, L3 = Lx1 + t(Ly1), Lx2 + t(Ly2), Lx3 + t(Ly3)
     if prob.gravity != 0.0:
@@ -598,25 +671,26 @@ def time_step(prob, alpha, rule='production', cfl=0.6):
     return cfl / den
 
 
-def step(prob, U, V, W, dt, alphas=None):
-    """One SSP-RK3 step with the modified derivatives as the RK base.
-    ``alphas``: optional fixed LF alphas for the three stages (frozen-alpha
-    mode used for the adjoint); otherwise each stage takes alpha from its own
-    state. Returns (U, V, W, alphas_used)."""
+def step(prob, U, V, W, dt, alphas=None, t=0.0):
+    """One SSP-RK3 step from time t with the modified derivatives as the RK
+    base; the stages see the times t, t + dt, t + dt/2 (SSP-RK3's abscissae,
+    for time-dependent boundaries). ``alphas``: optional fixed LF alphas for
+    the three stages (frozen-alpha mode used for the adjoint); otherwise each
+    stage takes alpha from its own state. Returns (U, V, W, alphas_used)."""
     a = [None, None, None] if alphas is None else list(alphas)
     two = prob.dim == 2
     a[0] = a[0] if a[0] is not None else max_speed(prob, U)
-    L1, L2, L3, vt0, wt0 = rhs(prob, U, V, W, a[0])
+    L1, L2, L3, vt0, wt0 = rhs(prob, U, V, W, a[0], t)
     U1 = U + dt * L1
     V1 = vt0 + dt * L2
     W1 = wt0 + dt * L3 if two else None
     a[1] = a[1] if a[1] is not None else max_speed(prob, U1)
-    L1, L2, L3, vt1, wt1 = rhs(prob, U1, V1, W1, a[1])
+    L1, L2, L3, vt1, wt1 = rhs(prob, U1, V1, W1, a[1], t + dt)
     U2 = 0.75 * U + 0.25 * (U1 + dt * L1)
     V2 = 0.75 * vt0 + 0.25 * (vt1 + dt * L2)
     W2 = 0.75 * wt0 + 0.25 * (wt1 + dt * L3) if two else None
     a[2] = a[2] if a[2] is not None else max_speed(prob, U2)
-    L1, L2, L3, vt2, wt2 = rhs(prob, U2, V2, W2, a[2])
+    L1, L2, L3, vt2, wt2 = rhs(prob, U2, V2, W2, a[2], t + 0.5 * dt)
     U3 = U / 3.0 + 2.0 / 3.0 * (U2 + dt * L1)
     V3 = vt0 / 3.0 + 2.0 / 3.0 * (vt2 + dt * L2)
     W3 = wt0 / 3.0 + 2.0 / 3.0 * (wt2 + dt * L3) if two else None
@@ -643,7 +717,7 @@ def run(prob, U, V, W, t_end, rule='production', cfl=0.6, max_steps=None, log=No
         last = t + dt >= t_end
         if last:
             dt = t_end - t
-        U, V, W, al = step(prob, U, V, W, dt, (alpha, None, None))
+        U, V, W, al = step(prob, U, V, W, dt, (alpha, None, None), t)
         t = t_end if last else t + dt
         log.steps += 1
         log.dts.append(dt)

@@ -624,14 +624,16 @@ HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
 
 // ------------------------------------------------------------- index maps
 // Boundary codes, as in the C ABI.
-constexpr int kBcPeriodic = 0, kBcTransmissive = 1, kBcReflective = 2, kBcDirichlet = 3;
+constexpr int kBcPeriodic = 0, kBcTransmissive = 1, kBcReflective = 2, kBcDirichlet = 3,
+              kBcSplit = 4;
 
 // Ghost cells by index map: periodic wraps, transmissive clamps (copies the
 // nearest interior cell), reflective mirrors (ghost -1-k is the image of
 // cell k, ghost n+k of cell n-1-k). Any integer i is accepted and the result
 // is always in [0, n): lanes further out than the mirror reaches (only the
 // two ghosts next to a wall enter the scheme) are clamped to an edge cell.
-// Fixed-state (Dirichlet) ghosts are clamped too; their values are replaced.
+// Fixed-state (Dirichlet) and split-side ghosts are clamped too; the kernels
+// replace or re-map them.
 HWENO_HD int map_index(int i, int n, int lo, int hi) {
   if (i >= 0 && i < n) return i;
   const int side = i < 0 ? lo : hi;

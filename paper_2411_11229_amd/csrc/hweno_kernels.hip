@@ -27,6 +27,14 @@ namespace hweno {
 
 enum Mode { kRhs = 0, kStage1 = 1, kStage2 = 2, kStage3 = 3 };
 
+// A split y side (see hweno_split): ghost (x, y) follows kind[0] where
+// x < x0 + slope y + speed t, else kind[1].
+struct SplitRule {
+  double x0, slope, speed;
+  int kind[2];
+  double state[2][4];
+};
+
 template <typename T>
 struct StageArgs {
   const T* U;  const T* V;  const T* W;   // stage state X (W null in 1D)
@@ -45,6 +53,9 @@ struct StageArgs {
   int iface;                              // host side: interface characteristic basis
   double gs[4][4];                        // fixed (Dirichlet) ghost states per side
   double gravity;                         // g of the (euler2d-s) source
+  SplitRule sp[2];                        // split y sides (low, high)
+  const double* t0;                       // step start time (device), null: t = 0
+  double tc;                              // this stage's time: t0 + tc dt
   Scheme s;
 };
 
@@ -222,10 +233,25 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
 // use the kernel without this code, whose register allocation it would
 // disturb.
 template <class Sys, bool WALLS, typename T>
-__device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol, bool xwall,
-                                         bool xm, int xf, T (&U)[Sys::NC], T (&V)[Sys::NC],
-                                         T (&W)[Sys::NC]) {
-  const int gr = map_index(r, A.ny, A.bc[2], A.bc[3]);
+__device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int col, int gcol,
+                                         bool xwall, bool xm, int xf, T (&U)[Sys::NC],
+                                         T (&V)[Sys::NC], T (&W)[Sys::NC]) {
+  int gr = map_index(r, A.ny, A.bc[2], A.bc[3]);
+  // split side: this lane's rule from its x, the ghost row's y and the
+  // stage time (0: transmissive, 1: reflective, 2 + k: fixed state k)
+  int split_rule = -1;
+  if constexpr (WALLS) {
+    const int yside = r < 0 ? 0 : (r >= A.ny ? 1 : -1);
+    if (yside >= 0 && A.bc[2 + yside] == kBcSplit) {
+      const SplitRule& sr = A.sp[yside];
+      const double t = A.t0 ? *A.t0 + A.tc * *A.dt : 0.0;
+      const double xs = sr.x0 + sr.slope * ((r + 0.5) * A.s.dy) + sr.speed * t;
+      const int k = (col + 0.5) * A.s.dx < xs ? 0 : 1;
+      const int kind = sr.kind[k];
+      split_rule = kind == kBcReflective ? 1 : (kind == kBcDirichlet ? 2 + k : 0);
+      if (split_rule == 1) gr = map_index(r, A.ny, kBcReflective, kBcReflective);
+    }
+  }
   const int off = gr * A.nx + gcol;
 #pragma unroll
   for (int c = 0; c < Sys::NC; ++c) {
@@ -248,13 +274,22 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int gcol,
       mirror_state<Sys, 0>(xm, W);
       if (xf >= 0) fix(xf);
     }
-    if (mirrored(r, A.ny, A.bc[2], A.bc[3])) {
+    if (mirrored(r, A.ny, A.bc[2], A.bc[3]) || split_rule == 1) {
       mirror_state<Sys, 1>(true, U);
       mirror_state<Sys, 1>(true, V);
       mirror_normal_derivative<Sys, 1>(true, W);
     }
     const int yf = fixed_side(r, A.ny, A.bc[2], A.bc[3]);
     if (yf >= 0) fix(2 + yf);
+    if (split_rule >= 2) {
+      const SplitRule& sr = A.sp[r < 0 ? 0 : 1];
+#pragma unroll
+      for (int c = 0; c < Sys::NC; ++c) {
+        U[c] = T(sr.state[split_rule - 2][c]);
+        V[c] = T(0);
+        W[c] = T(0);
+      }
+    }
   }
 }
 
@@ -303,12 +338,12 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   unsigned flag = 0;
 
   T Un[NC], Vn[NC], Wn[NC];
-  load_row<Sys, WALLS>(A, y0 - 2, gcol, xwall, xm, xf, Un, Vn, Wn);
+  load_row<Sys, WALLS>(A, y0 - 2, col, gcol, xwall, xm, xf, Un, Vn, Wn);
   for (int r = y0 - 2; r < y1 + 2; ++r) {
     T Uc[NC], Vc[NC], Wc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) { Uc[c] = Un[c]; Vc[c] = Vn[c]; Wc[c] = Wn[c]; }
-    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, r + 1, gcol, xwall, xm, xf, Un, Vn, Wn);  // prefetch
+    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, r + 1, col, gcol, xwall, xm, xf, Un, Vn, Wn);  // prefetch
     // RK base of this iteration's output row, loaded early to hide latency
     T Bu[NC], Bv[NC], Bw[NC];
     if (MODE >= kStage2 && r >= y0 + 2 && out_col) {
@@ -520,6 +555,7 @@ struct StepScalars {
   double alpha1[2];               // stage-1 alphas
   unsigned long long acc[4];      // stage-2 and stage-3 alphas (atomic max bits)
   double dt;
+  double t0;                      // the step's start time
   int active;
   unsigned flags;
 };
@@ -548,6 +584,7 @@ __global__ __launch_bounds__(256) void dt_kernel(const double* partial, int n, D
   if (a.rule == HWENO_DT_FIXED) dt = a.dt_fixed;
   else dt = a.cfl / (a.dim == 2 ? ax / a.hx + ay / a.hy : ax / a.hx);
   const double t0 = *t;
+  sc->t0 = t0;
   int active = t0 < a.t_end ? 1 : 0;
   if (active) {
     if (t0 + dt >= a.t_end) {
@@ -1189,6 +1226,19 @@ struct Geometry {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// A finite Euler state (rho, momenta..., E) with rho > 0 and P > 0.
+bool admissible_state(const double* q, int nc, double gas) {
+  for (int c = 0; c < nc; ++c)
+    if (!std::isfinite(q[c])) return false;
+  double m2 = 0.0;
+  for (int c = 1; c < nc - 1; ++c) m2 += q[c] * q[c];
+  return q[0] > 0.0 && (gas - 1.0) * (q[nc - 1] - 0.5 * m2 / q[0]) > 0.0;
+}
+
+bool has_split(const hweno_problem* p) {
+  return p->bc[2] == HWENO_SPLIT || p->bc[3] == HWENO_SPLIT;
+}
+
 hweno_status validate(const hweno_problem* p) {
   if (!p) return HWENO_EINVAL;
   if (p->dim != 1 && p->dim != 2) return HWENO_EINVAL;
@@ -1206,20 +1256,30 @@ hweno_status validate(const hweno_problem* p) {
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return HWENO_EINVAL;
   for (int k = 0; k < 4; ++k) {
     if (p->bc[k] != HWENO_PERIODIC && p->bc[k] != HWENO_TRANSMISSIVE &&
-        p->bc[k] != HWENO_REFLECTIVE && p->bc[k] != HWENO_DIRICHLET)
+        p->bc[k] != HWENO_REFLECTIVE && p->bc[k] != HWENO_DIRICHLET && p->bc[k] != HWENO_SPLIT)
       return HWENO_EINVAL;
+    if (p->bc[k] == HWENO_SPLIT) {
+      if (k < 2 || p->dim != 2 || p->system != HWENO_EULER) return HWENO_EINVAL;
+      const hweno_split& sp = p->split[k - 2];
+      if (!std::isfinite(sp.x0) || !std::isfinite(sp.slope) || !std::isfinite(sp.speed))
+        return HWENO_EINVAL;
+      for (int j = 0; j < 2; ++j) {
+        const int kind = sp.kind[j];
+        if (kind != HWENO_TRANSMISSIVE && kind != HWENO_REFLECTIVE && kind != HWENO_DIRICHLET)
+          return HWENO_EINVAL;
+        if (kind == HWENO_DIRICHLET && !admissible_state(sp.state[j], 4, p->gas_gamma))
+          return HWENO_EINVAL;
+      }
+    }
     // reflective walls are defined for the Euler equations only
     if (p->bc[k] == HWENO_REFLECTIVE && p->system != HWENO_EULER) return HWENO_EINVAL;
     if (p->bc[k] == HWENO_DIRICHLET && (k < 2 || p->dim == 2)) {
       const double* q = p->bc_state[k];
       const int nc = p->system == HWENO_EULER ? p->dim + 2 : 1;
-      for (int c = 0; c < nc; ++c)
-        if (!std::isfinite(q[c])) return HWENO_EINVAL;
       if (p->system == HWENO_EULER) {
-        double m2 = 0.0;
-        for (int c = 1; c < nc - 1; ++c) m2 += q[c] * q[c];
-        if (!(q[0] > 0.0) || !((p->gas_gamma - 1.0) * (q[nc - 1] - 0.5 * m2 / q[0]) > 0.0))
-          return HWENO_EINVAL;
+        if (!admissible_state(q, nc, p->gas_gamma)) return HWENO_EINVAL;
+      } else if (!std::isfinite(q[0])) {
+        return HWENO_EINVAL;
       }
     }
   }
@@ -1439,7 +1499,8 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
       }
     };
     bool walls = false;
-    for (int k = 0; k < 4; ++k) walls = walls || A.bc[k] == kBcReflective || A.bc[k] == kBcDirichlet;
+    for (int k = 0; k < 4; ++k)
+      walls = walls || A.bc[k] == kBcReflective || A.bc[k] == kBcDirichlet || A.bc[k] == kBcSplit;
     const int var = (walls ? kVarWalls : 0) | (Sys::kChar && A.iface ? kVarIface : 0) |
                     (Sys::kChar && A.gravity != 0.0 ? kVarSource : 0);
     if constexpr (Sys::kChar) {
@@ -1475,6 +1536,17 @@ StageArgs<T> base_args(const hweno_problem* p) {
   for (int k = 0; k < 4; ++k)
     for (int c = 0; c < 4; ++c) A.gs[k][c] = p->bc_state[k][c];
   A.gravity = p->system == HWENO_EULER && p->dim == 2 ? p->gravity : 0.0;
+  for (int k = 0; k < 2; ++k) {
+    A.sp[k].x0 = p->split[k].x0;
+    A.sp[k].slope = p->split[k].slope;
+    A.sp[k].speed = p->split[k].speed;
+    for (int j = 0; j < 2; ++j) {
+      A.sp[k].kind[j] = p->split[k].kind[j];
+      for (int c = 0; c < 4; ++c) A.sp[k].state[j][c] = p->split[k].state[j][c];
+    }
+  }
+  A.t0 = nullptr;
+  A.tc = 0.0;
   A.s = make_scheme(p);
   return A;
 }
@@ -1768,6 +1840,7 @@ hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void*
     A.dt = &wl.sc->dt;
     A.active = &wl.sc->active;
     A.flags = &wl.sc->flags;
+    A.t0 = &wl.sc->t0;            // stage times t0, t0 + dt, t0 + dt/2
     auto mark = [&](int k) -> bool {
       return !events || hipEventRecord(events[k], stream) == hipSuccess;
     };
@@ -1789,6 +1862,7 @@ hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void*
     A.alpha = (const double*)&wl.sc->acc[0];
     A.alpha_next = &wl.sc->acc[2];
     A.alpha_rec = alpha_rec ? alpha_rec + 2 : nullptr;
+    A.tc = 1.0;
     if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
     if (!mark(2)) return HWENO_EDEVICE;
     // stage 3: X^(2) -> X^{n+1}, in place on (u, v, w)
@@ -1797,6 +1871,7 @@ hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void*
     A.alpha = (const double*)&wl.sc->acc[2];
     A.alpha_next = nullptr;
     A.alpha_rec = alpha_rec ? alpha_rec + 4 : nullptr;
+    A.tc = 0.5;
     if ((s2 = launch_stage<Sys, T, DIM>(kStage3, A, sy, stream)) != HWENO_OK) return s2;
     if (!mark(3)) return HWENO_EDEVICE;
     return HWENO_OK;
@@ -1811,6 +1886,7 @@ hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w
   if (!u || !v || !dt || !alpha_rec || !ws) return HWENO_EINVAL;
   if (p->dim == 2 && !w) return HWENO_EINVAL;
   if (p->dim == 1 && w) return HWENO_EINVAL;
+  if (has_split(p)) return HWENO_EUNSUPPORTED;   // no step time here
   if (u_out) {
     if (!v_out || (p->dim == 2) != (w_out != nullptr)) return HWENO_EINVAL;
     const void* ins[4] = {u, v, w, stages};
@@ -1868,6 +1944,7 @@ hweno_status hweno_adjoint_step(const hweno_problem* p, const void* u_n, const v
   if (!u_n || !v_n || !dt || !alpha_rec || !lam_u_in || !lam_v_in || !lam_u_out || !lam_v_out || !ws)
     return HWENO_EINVAL;
   if (p->system == HWENO_EULER && p->char_basis == HWENO_BASIS_INTERFACE) return HWENO_EUNSUPPORTED;
+  if (has_split(p)) return HWENO_EUNSUPPORTED;
   if (two && (!w_n || !lam_w_in || !lam_w_out)) return HWENO_EINVAL;
   if (!two && (w_n || lam_w_in || lam_w_out)) return HWENO_EINVAL;
   const void* ins[8] = {u_n, v_n, w_n, stages, lam_u_in, lam_v_in, lam_w_in, nullptr};

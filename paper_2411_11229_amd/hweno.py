@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, 'libhweno.so')
 
 SYSTEMS = {'advection': 0, 'burgers': 1, 'euler': 2}
-BCS = {'periodic': 0, 'transmissive': 1, 'reflective': 2, 'dirichlet': 3}
+BCS = {'periodic': 0, 'transmissive': 1, 'reflective': 2, 'dirichlet': 3, 'split': 4}
 PRECISIONS = {'f64': 0, 'f32': 1}
 BASES = {'cell': 0, 'interface': 1}
 DT_RULES = {'production': 0, 'accuracy': 1, 'fixed': 2}
@@ -32,6 +32,11 @@ class HwenoError(RuntimeError):
         self.code = code
 
 
+class _CSplit(ctypes.Structure):
+    _fields_ = [('x0', ctypes.c_double), ('slope', ctypes.c_double), ('speed', ctypes.c_double),
+                ('kind', ctypes.c_int32 * 2), ('state', (ctypes.c_double * 4) * 2)]
+
+
 class _CProblem(ctypes.Structure):
     _fields_ = [('dim', ctypes.c_int32), ('nx', ctypes.c_int32), ('ny', ctypes.c_int32),
                 ('dx', ctypes.c_double), ('dy', ctypes.c_double), ('system', ctypes.c_int32),
@@ -40,7 +45,7 @@ class _CProblem(ctypes.Structure):
                 ('d0', ctypes.c_double), ('eps', ctypes.c_double),
                 ('bc', ctypes.c_int32 * 4), ('precision', ctypes.c_int32),
                 ('char_basis', ctypes.c_int32), ('bc_state', (ctypes.c_double * 4) * 4),
-                ('gravity', ctypes.c_double)]
+                ('gravity', ctypes.c_double), ('split', _CSplit * 2)]
 
 
 _P = ctypes.c_void_p
@@ -105,6 +110,7 @@ class Problem:
     basis: str = 'cell'               # characteristic basis: 'cell' | 'interface'
     bc_state: tuple = (None, None, None, None)   # conserved states of 'dirichlet' sides
     gravity: float = 0.0              # g of the (euler2d-s) source, 2D Euler only
+    split: tuple = (None, None)       # y_lo / y_hi split rules: dict(x0, slope, speed, kinds, states)
 
     def __post_init__(self):
         if self.gamma0 is None:
@@ -138,6 +144,17 @@ class Problem:
                 for c, v in enumerate(st):
                     p.bc_state[k][c] = float(v)
         p.gravity = float(self.gravity)
+        for k, sp in enumerate(self.split):
+            if sp is None:
+                continue
+            c = p.split[k]
+            c.x0, c.slope, c.speed = sp['x0'], sp['slope'], sp['speed']
+            for j in range(2):
+                c.kind[j] = BCS[sp['kinds'][j]]
+                st = (sp.get('states') or (None, None))[j]
+                if st is not None:
+                    for q, v in enumerate(st):
+                        c.state[j][q] = float(v)
         return p
 
 

@@ -21,6 +21,7 @@ stand-ins with the shapes and value ranges of its examples):
   * ``blast_wave_1d``    Example 4.4 (Woodward-Colella blast waves between
     two reflective walls).
   * ``rayleigh_taylor``  Example 4.11 (gravity source, walls, fixed states).
+  * ``double_mach``      Example 4.7 (double Mach reflection).
   * ``with_bc``          any of the above with other boundary conditions.
 """
 import math
@@ -62,6 +63,8 @@ class Workload:
             kw['bc_state'] = tuple(self.bc_state)
         if self.gravity != 0.0:
             kw['gravity'] = self.gravity
+        if 'split' in self.extra:
+            kw['split'] = tuple(self.extra['split'])
         return kw
 
 
@@ -176,6 +179,39 @@ def rayleigh_taylor(nx=60, g=5.0 / 3.0):
                     bc=('reflective', 'reflective', 'dirichlet', 'dirichlet'), gas_gamma=g,
                     t_end=1.95, x=x, y=y, bc_state=(None, None, cons(2.0, 1.0), cons(1.0, 2.5)),
                     gravity=1.0)
+
+
+def double_mach(nx=1600, g=1.4):
+    """Example 4.7 on [0, 4] x [0, 1] with nx x nx/4 cells: a Mach 10 shock at
+    60 degrees to the x-axis through (1/6, 0); post-shock (rho, u, v, P) =
+    (8, 8.25 cos(pi/6), -8.25 sin(pi/6), 116.5) left of x = 1/6 + y/sqrt(3),
+    (1.4, 0, 0, 1) right of it; V = W = 0. Boundaries: the post-shock state on
+    the left (inflow), transmissive on the right (outflow), on the bottom the
+    post-shock state for x < 1/6 and a reflective wall beyond, on the top the
+    exact motion of the shock along the line y = 1, x_s = 1/6 + (1 + 20 t)/
+    sqrt(3) (post-shock state to its left, pre-shock to its right); T = 0.2.
+    The split boundaries are given as dicts (x0, slope, speed, kinds, states)
+    for the problem's ``split``."""
+    ny = nx // 4
+    x, hx = centres(nx, 0.0, 4.0)
+    y, hy = centres(ny, 0.0, 1.0)
+    X, Y = np.meshgrid(x, y)
+    r3 = math.sqrt(3.0)
+    post = (8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
+    pre = (1.4, 0.0, 0.0, 1.0)
+    left = X < 1.0 / 6.0 + Y / r3
+    rho, u, v, p = (np.where(left, a, b) for a, b in zip(post, pre))
+    zero = np.zeros_like(X)
+    U, V = conserved_2d(rho, u, v, p, zero, zero, zero, zero, g)
+    cons = lambda q: (q[0], q[0] * q[1], q[0] * q[2], q[3] / (g - 1.0) + 0.5 * q[0] * (q[1] ** 2 + q[2] ** 2))
+    bottom = dict(x0=1.0 / 6.0, slope=0.0, speed=0.0, kinds=('dirichlet', 'reflective'),
+                  states=(cons(post), None))
+    top = dict(x0=1.0 / 6.0 + 1.0 / r3, slope=0.0, speed=20.0 / r3, kinds=('dirichlet', 'dirichlet'),
+               states=(cons(post), cons(pre)))
+    return Workload('double_mach', 2, 'euler', nx, ny, hx, hy, U, V, V.copy(),
+                    bc=('dirichlet', 'transmissive', 'split', 'split'), gas_gamma=g, t_end=0.2,
+                    x=x, y=y, bc_state=(cons(post), None, None, None),
+                    extra=dict(split=(bottom, top), post=post, pre=pre))
 
 
 def with_bc(w, bc):

@@ -1,0 +1,100 @@
+"""Pins of the oracle's split (position- and time-dependent) y-sides and of
+Example 4.7's input (double Mach reflection).
+
+* A split side whose two kinds agree is that plain boundary; a split point
+  beyond the domain leaves the first kind everywhere.
+* The post- and pre-shock states of Example 4.7 satisfy the Rankine-Hugoniot
+  conditions of a Mach 10 shock (normal speed 10 into gas at rest with sound
+  speed 1) in the shock's normal direction.
+* An oblique Mach 10 shock between split sides that follow its exact motion
+  along the boundary lines (x_s = 1/6 + 20 t/sqrt(3) at y = 0,
+  1/6 + (1 + 20 t)/sqrt(3) at y = 1) moves at the exact speed (conservation
+  fixes it): after 40 steps the density mid-level crossing of every row lies
+  within 1.5 cells of 1/6 + (y + 20 t)/sqrt(3). With the sides' motion
+  switched off the top and bottom rows lag by many cells.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hweno as O
+from paper_2411_11229_amd import workloads as WL
+
+R3 = math.sqrt(3.0)
+
+
+def _problem(w, split):
+    kw = w.problem_kwargs()
+    kw['split'] = split
+    return O.Problem(**kw)
+
+
+@pytest.mark.parametrize("kind", ['reflective', 'transmissive', 'dirichlet'])
+def test_split_with_equal_kinds_is_the_plain_side(kind):
+    w = WL.euler2d_quadrants(20, seed=4601, ny=14)
+    st = tuple(w.U[:, 0, 3])
+    sp = dict(x0=0.37, slope=0.4, speed=3.0, kinds=(kind, kind), states=(st, st))
+    a = _problem(w, (sp, sp))
+    a.bc = ('transmissive', 'transmissive', 'split', 'split')
+    b = O.Problem(**dict(w.problem_kwargs(), bc=('transmissive', 'transmissive', kind, kind),
+                         bc_state=(None, None, st, st)))
+    alpha = O.max_speed(b, w.U)
+    for x, y in zip(O.rhs(a, w.U, w.V, w.W, alpha, t=0.3), O.rhs(b, w.U, w.V, w.W, alpha)):
+        np.testing.assert_allclose(x, y, rtol=0, atol=1e-13 * max(1.0, np.max(np.abs(y))))
+
+
+def test_split_point_beyond_the_domain_keeps_the_first_kind():
+    w = WL.euler2d_smooth(18, seed=3601, ny=12)
+    sp = dict(x0=50.0, slope=0.0, speed=0.0, kinds=('reflective', 'transmissive'), states=(None, None))
+    a = _problem(w, (sp, sp))
+    a.bc = ('periodic', 'periodic', 'split', 'split')
+    b = O.Problem(**dict(w.problem_kwargs(), bc=('periodic', 'periodic', 'reflective', 'reflective')))
+    alpha = O.max_speed(b, w.U)
+    for x, y in zip(O.rhs(a, w.U, w.V, w.W, alpha), O.rhs(b, w.U, w.V, w.W, alpha)):
+        np.testing.assert_allclose(x, y, rtol=0, atol=1e-13 * max(1.0, np.max(np.abs(y))))
+
+
+def test_double_mach_states_satisfy_rankine_hugoniot():
+    w = WL.double_mach(64)
+    g = w.gas_gamma
+    (r2, u2, v2, p2), (r1, u1, v1, p1) = w.extra['post'], w.extra['pre']
+    n = (math.cos(math.pi / 6), -math.sin(math.pi / 6))     # shock normal, 60 degrees to x
+    s = 10.0 * math.sqrt(g * p1 / r1)                       # Mach 10 into the gas at rest
+    un2, un1 = u2 * n[0] + v2 * n[1], u1 * n[0] + v1 * n[1]
+    ut2 = -u2 * n[1] + v2 * n[0]
+    m1, m2 = r1 * (un1 - s), r2 * (un2 - s)
+    assert m2 == pytest.approx(m1, rel=1e-3)
+    assert r2 * (un2 - s) ** 2 + p2 == pytest.approx(r1 * (un1 - s) ** 2 + p1, rel=1e-3)
+    h = lambda r, p: g / (g - 1.0) * p / r
+    assert h(r2, p2) + 0.5 * (un2 - s) ** 2 == pytest.approx(h(r1, p1) + 0.5 * (un1 - s) ** 2, rel=1e-3)
+    assert abs(ut2) < 1e-12                                 # no tangential velocity jump
+
+
+@pytest.mark.parametrize("moving", [True, False])
+def test_oblique_shock_moves_at_the_exact_speed(moving):
+    w = WL.double_mach(96)
+    post, pre = w.extra['split'][1]['states']
+    sp = lambda x0: dict(x0=x0, slope=0.0, speed=20.0 / R3 if moving else 0.0,
+                         kinds=('dirichlet', 'dirichlet'), states=(post, pre))
+    p = _problem(w, (sp(1.0 / 6.0), sp(1.0 / 6.0 + 1.0 / R3)))
+    U, V, W, t = w.U, w.V, w.W, 0.0
+    for k in range(40):
+        alpha = O.max_speed(p, U)
+        dt = O.time_step(p, alpha, 'production', 0.1 if k < 5 else 0.6)
+        U, V, W, _ = O.step(p, U, V, W, dt, (alpha, None, None), t)
+        t += dt
+    mid = 0.5 * (post[0] + pre[0])
+    err = []
+    for j, y in enumerate(w.y):
+        r = U[0, j]
+        i = int(np.argmax(r < mid))
+        xc = w.x[i - 1] + (mid - r[i - 1]) * (w.x[i] - w.x[i - 1]) / (r[i] - r[i - 1])
+        err.append((xc - (1.0 / 6.0 + (y + 20.0 * t) / R3)) / w.dx)
+    worst = float(np.max(np.abs(err)))
+    print(f't = {t:.4f}: worst shock offset {worst:.2f} cells')
+    assert np.isfinite(worst)
+    if moving:
+        assert worst <= 1.5
+    else:
+        assert worst > 5.0
