@@ -95,6 +95,21 @@ def test_fixed_states_and_gravity_validated(lib):
                                 bc_state=((0.3,), (0.1,), None, None)))[0] == 0
 
 
+def test_split_sides_validated(lib):
+    st = (1.0, 0.2, -0.1, 2.5)
+    sp = dict(x0=0.3, slope=0.0, speed=1.0, kinds=('dirichlet', 'reflective'), states=(st, None))
+    ok = dict(bc=('transmissive', 'transmissive', 'split', 'split'), split=(sp, sp))
+    assert _ws_bytes(lib, _prob(**ok))[0] == 0
+    # split on an x side, in 1D, for a scalar law; bad kinds and states
+    assert _ws_bytes(lib, _prob(bc=('split', 'transmissive', 'periodic', 'periodic'), split=(sp, sp)))[0] == -1
+    assert _ws_bytes(lib, _prob(system='burgers', **ok))[0] == -1
+    bad_kind = dict(sp, kinds=('periodic', 'reflective'))
+    assert _ws_bytes(lib, _prob(bc=ok['bc'], split=(bad_kind, sp)))[0] == -1
+    bad_state = dict(sp, states=((1.0, 5.0, 0.0, 1.0), None))
+    assert _ws_bytes(lib, _prob(bc=ok['bc'], split=(sp, bad_state)))[0] == -1
+    assert _ws_bytes(lib, _prob(bc=ok['bc'], split=(dict(sp, speed=float('nan')), sp)))[0] == -1
+
+
 def test_interface_basis_accepted(lib):
     assert _ws_bytes(lib, _prob(basis='interface'))[0] == 0
     assert _ws_bytes(lib, _prob(system='burgers', basis='interface'))[0] == 0
