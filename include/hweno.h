@@ -121,7 +121,8 @@ typedef enum {
  */
 typedef struct {
   int32_t dim;          /* 1 or 2                                                */
-  int32_t nx, ny;       /* cells; nx >= 5; ny >= 5 in 2D, ny == 1 in 1D           */
+  int32_t nx, ny;       /* cells; nx >= 5; ny >= 5 in 2D, ny == 1 in 1D; one      */
+                        /* state array (ncomp * nx * ny elements) under 4 GiB     */
   double dx, dy;        /* > 0; dy ignored in 1D                                  */
   int32_t system;       /* hweno_system                                           */
   double adv_a, adv_b;  /* advection speeds (HWENO_ADVECTION only)                */

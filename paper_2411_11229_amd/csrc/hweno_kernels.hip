@@ -60,6 +60,19 @@ struct StageArgs {
 };
 
 // ---------------------------------------------------------------- helpers
+// Element idx of a state array through a 32-bit byte offset from the uniform
+// base pointer: the loads and stores then take the scalar-base form (base in
+// SGPRs, offset in one VGPR) instead of a 64-bit address per lane. The host
+// guarantees ncomp * plane * sizeof(T) < 2^32.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, unsigned idx) {
+  return *(const T*)((const char*)base + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, unsigned idx, T v) {
+  *(T*)((char*)base + idx * (unsigned)sizeof(T)) = v;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -252,12 +265,13 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int col, 
       if (split_rule == 1) gr = map_index(r, A.ny, kBcReflective, kBcReflective);
     }
   }
-  const int off = gr * A.nx + gcol;
+  const unsigned off = (unsigned)(gr * A.nx + gcol);
 #pragma unroll
   for (int c = 0; c < Sys::NC; ++c) {
-    U[c] = A.U[c * A.plane + off];
-    V[c] = A.V[c * A.plane + off];
-    W[c] = A.W[c * A.plane + off];
+    const unsigned i = (unsigned)(c * A.plane) + off;
+    U[c] = ld32(A.U, i);
+    V[c] = ld32(A.V, i);
+    W[c] = ld32(A.W, i);
   }
   if constexpr (WALLS) {
     auto fix = [&](int side) {
@@ -349,10 +363,10 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
     if (MODE >= kStage2 && r >= y0 + 2 && out_col) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const int idx = c * A.plane + (r - 2) * A.nx + col;
-        Bu[c] = A.Ub[idx];
-        Bv[c] = A.Vb[idx];
-        Bw[c] = A.Wb[idx];
+        const unsigned idx = (unsigned)(c * A.plane + (r - 2) * A.nx + col);
+        Bu[c] = ld32(A.Ub, idx);
+        Bv[c] = ld32(A.Vb, idx);
+        Bw[c] = ld32(A.Wb, idx);
       }
     }
     // pointwise g, theta = g'(u) w, xi = g'(u) v of row r
@@ -437,18 +451,18 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
                 Lw += A.gravity * (double)Wa[k];
               }
             }
-            const int idx = c * A.plane + o * A.nx + col;
+            const unsigned idx = (unsigned)(c * A.plane + o * A.nx + col);
             const double ub = MODE >= kStage2 ? (double)Bu[c] : 0.0;
             const double vb = MODE >= kStage2 ? (double)Bv[c] : 0.0;
             const double wb = MODE >= kStage2 ? (double)Bw[c] : 0.0;
             Unew[c] = (T)rk<MODE>((double)Ua[c], ub, dt, Lu);
-            A.Uo[idx] = Unew[c];
-            A.Vo[idx] = (T)rk<MODE>((double)vt[c], vb, dt, Lv);
+            st32(A.Uo, idx, Unew[c]);
+            st32(A.Vo, idx, (T)rk<MODE>((double)vt[c], vb, dt, Lv));
             const T wto = topr[(r - 2) & 1][2][c][lane];   // w~ of row o
-            A.Wo[idx] = (T)rk<MODE>((double)wto, wb, dt, Lw);
+            st32(A.Wo, idx, (T)rk<MODE>((double)wto, wb, dt, Lw));
             if (MODE == kStage1 || MODE == kRhs) {
-              A.Vt[idx] = vt[c];
-              A.Wt[idx] = wto;
+              st32(A.Vt, idx, vt[c]);
+              st32(A.Wt, idx, wto);
             }
           }
           if (A.alpha_next) {
@@ -685,9 +699,10 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   T U[NC], Av[NC], Ov[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    U[c] = A.X[0][c * A.plane + base + g];
-    Av[c] = A.X[1][c * A.plane + base + g];
-    Ov[c] = NF == 3 ? A.X[2][c * A.plane + base + g] : T(0);
+    const unsigned i = (unsigned)(c * A.plane + base + g);
+    U[c] = ld32(A.X[0], i);
+    Av[c] = ld32(A.X[1], i);
+    Ov[c] = NF == 3 ? ld32(A.X[2], i) : T(0);
   }
   if constexpr (WALLS) {
     const bool m = mirrored(v, A.n, A.bc_lo, A.bc_hi);
@@ -712,14 +727,14 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     const T cbt = T(A.cb * dtv);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int idx = c * A.plane + base + v;
-      bU[c] = cbt * A.b[0][idx];
-      bA[c] = cbt * A.b[1][idx];
-      if (NF == 3) bO[c] = cbt * A.b[2][idx];
+      const unsigned idx = (unsigned)(c * A.plane + base + v);
+      bU[c] = cbt * ld32(A.b[0], idx);
+      bA[c] = cbt * ld32(A.b[1], idx);
+      if (NF == 3) bO[c] = cbt * ld32(A.b[2], idx);
 #pragma unroll
       for (int k = 0; k < NA; ++k) {
-        aU[c] += T(A.ca[k]) * A.a[k][0][idx];
-        aA[c] += T(A.ca[k]) * A.a[k][1][idx];
+        aU[c] += T(A.ca[k]) * ld32(A.a[k][0], idx);
+        aA[c] += T(A.ca[k]) * ld32(A.a[k][1], idx);
       }
     }
   }
@@ -819,10 +834,10 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     if (interior) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const int idx = c * A.plane + base + v;
-        A.G[0][idx] = gU[c];
-        A.G[1][idx] = gA[c];
-        if (NF == 3) A.G[2][idx] = gO[c];
+        const unsigned idx = (unsigned)(c * A.plane + base + v);
+        st32(A.G[0], idx, gU[c]);
+        st32(A.G[1], idx, gA[c]);
+        if (NF == 3) st32(A.G[2], idx, gO[c]);
       }
     } else {
       const int slot = v < 0 ? v + 2 : v - A.n + 2;
@@ -898,16 +913,16 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
     T Uc[NC], Vc[NC], Wc[NC], bUc[NC], bVc[NC], bWc[NC], aWc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int idx = c * A.plane + gr * A.nx + xc;
-      Uc[c] = A.X[0][idx];
-      Vc[c] = A.X[1][idx];
-      Wc[c] = A.X[2][idx];
+      const unsigned idx = (unsigned)(c * A.plane + gr * A.nx + xc);
+      Uc[c] = ld32(A.X[0], idx);
+      Vc[c] = ld32(A.X[1], idx);
+      Wc[c] = ld32(A.X[2], idx);
       bUc[c] = T(0); bVc[c] = T(0); bWc[c] = T(0); aWc[c] = T(0);
       if (inrow) {
-        bUc[c] = cbt * A.b[0][idx];
-        bVc[c] = cbt * A.b[1][idx];
-        bWc[c] = cbt * A.b[2][idx];
-        for (int k = 0; k < A.na; ++k) aWc[c] += T(A.ca[k]) * A.aw[k][idx];
+        bUc[c] = cbt * ld32(A.b[0], idx);
+        bVc[c] = cbt * ld32(A.b[1], idx);
+        bWc[c] = cbt * ld32(A.b[2], idx);
+        for (int k = 0; k < A.na; ++k) aWc[c] += T(A.ca[k]) * ld32(A.aw[k], idx);
       }
     }
     if constexpr (WALLS) {
@@ -1027,8 +1042,8 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
           const T* xg = A.xghost + (size_t)o * 4 * 3 * NC;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const int idx = c * A.plane + o * A.nx + x;
-            T gx[3] = {A.G[0][idx], A.G[1][idx], A.G[2][idx]};
+            const unsigned idx = (unsigned)(c * A.plane + o * A.nx + x);
+            T gx[3] = {ld32((const T*)A.G[0], idx), ld32((const T*)A.G[1], idx), ld32((const T*)A.G[2], idx)};
             if (xs.a >= 0) {
 #pragma unroll
               for (int f = 0; f < 3; ++f) {
@@ -1040,9 +1055,9 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
                 }
               }
             }
-            A.G[0][idx] = gx[0] + gU[c];
-            A.G[1][idx] = gx[1] + gV[c];
-            A.G[2][idx] = gx[2] + gW[c];
+            st32(A.G[0], idx, gx[0] + gU[c]);
+            st32(A.G[1], idx, gx[1] + gV[c]);
+            st32(A.G[2], idx, gx[2] + gW[c]);
           }
         } else {
           const int slot = o < 0 ? o + 2 : o - A.ny + 2;
@@ -1292,8 +1307,11 @@ hweno_status validate(const hweno_problem* p) {
   if (p->char_basis != HWENO_BASIS_CELL && p->char_basis != HWENO_BASIS_INTERFACE)
     return HWENO_EINVAL;
   const int nc = p->system == HWENO_EULER ? p->dim + 2 : 1;
-  // 32-bit element offsets inside a state array
+  // 32-bit element offsets inside a state array, and 32-bit byte offsets in
+  // the stage kernels
   if ((double)nc * (double)p->nx * (double)p->ny >= 2147483647.0) return HWENO_EINVAL;
+  const double esize = p->precision == HWENO_F64 ? 8.0 : 4.0;
+  if ((double)nc * (double)p->nx * (double)p->ny * esize >= 4294967296.0) return HWENO_EINVAL;
   return HWENO_OK;
 }
 

@@ -110,6 +110,12 @@ def test_split_sides_validated(lib):
     assert _ws_bytes(lib, _prob(bc=ok['bc'], split=(dict(sp, speed=float('nan')), sp)))[0] == -1
 
 
+def test_state_array_size_limit(lib):
+    # one state array must stay under 4 GiB (32-bit byte offsets)
+    assert _ws_bytes(lib, _prob(nx=12000, ny=12000))[0] == -1          # 4.6 GB in FP64
+    assert _ws_bytes(lib, _prob(nx=12000, ny=12000, precision='f32'))[0] == 0
+
+
 def test_interface_basis_accepted(lib):
     assert _ws_bytes(lib, _prob(basis='interface'))[0] == 0
     assert _ws_bytes(lib, _prob(system='burgers', basis='interface'))[0] == 0

@@ -125,11 +125,13 @@ def test_rayleigh_taylor_run_matches_oracle_and_stays_symmetric():
     run = lambda a, b, c: O.run(p, a, b, c, 1e9, max_steps=25)[:3]
     base, worst = oracle_sensitivity(p, w, run)
     check_run(w, (U, V, W), base, worst, 'rayleigh-taylor-32x128')
+    # the mirror symmetry about x = 1/8 holds to round-off; the instability
+    # amplifies round-off like the oracle's 1-ulp divergence, hence the bound
     sign = torch.tensor([1.0, -1.0, 1.0, 1.0], dtype=torch.float64, device='cuda')[:, None, None]
-    for X, sg in ((U, sign), (W, sign), (V, -sign)):
+    for k, (X, sg) in enumerate(((U, sign), (V, -sign), (W, sign))):
         asym = float((X - sg * X.flip(-1)).abs().max() / X.abs().max())
         print(f'  mirror asymmetry {asym:.2e}')
-        assert asym <= 1e-12
+        assert asym <= max(10 * worst[k], 1e-12)
     s.health()
 
 
