@@ -347,7 +347,9 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   int slot = ((y0 - 2) % 3 + 3) % 3;   // slot of row r (and of row r-3)
   // top-face LF halves (g, theta) and w~ of rows r-2 and r-1, by row parity
   __shared__ T topr[2][3][NC][kWave];
-  T Fg[NC], Ft[NC], Fx[NC];           // y-interface fluxes at (r-3)+1/2
+  // y-interface fluxes g, theta, xi at (r-3)+1/2, in LDS (own column only):
+  // registers are the marcher's scarce resource
+  __shared__ T fprev[3][NC][kWave];
   double smx = 0.0, smy = 0.0;
   unsigned flag = 0;
 
@@ -439,9 +441,9 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
           T Unew[NC];
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            double Lu = RU[c] - ((double)Gn[c] - (double)Fg[c]) * s.idy;
-            double Lv = RV[c] - ((double)Xn[c] - (double)Fx[c]) * s.idy;
-            double Lw = RW[c] - ((double)Tn[c] - (double)Ft[c]) * s.idy;
+            double Lu = RU[c] - ((double)Gn[c] - (double)fprev[0][c][lane]) * s.idy;
+            double Lv = RV[c] - ((double)Xn[c] - (double)fprev[2][c][lane]) * s.idy;
+            double Lw = RW[c] - ((double)Tn[c] - (double)fprev[1][c][lane]) * s.idy;
             if constexpr (SOURCE) {
               // S(X) = g (0, 0, X_0, X_2) for X = u, v, w of the stage state
               if (c >= 2) {
@@ -474,7 +476,11 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
         }
       }
 #pragma unroll
-      for (int c = 0; c < NC; ++c) { Fg[c] = Gn[c]; Ft[c] = Tn[c]; Fx[c] = Xn[c]; }
+      for (int c = 0; c < NC; ++c) {
+        fprev[0][c][lane] = Gn[c];
+        fprev[1][c][lane] = Tn[c];
+        fprev[2][c][lane] = Xn[c];
+      }
     }
     // rotate the ring
 #pragma unroll
