@@ -223,3 +223,31 @@ def test_rayleigh_taylor_to_final_time():
     print(f'  mirror asymmetry {asym:.2e}')
     assert float(U[0, : w.ny // 2].min()) < 1.9
     assert float(U[0, w.ny // 2:].max()) > 1.1
+
+
+@pytest.mark.parametrize("name,w", [
+    ('rt-24x96-interface', WL.rayleigh_taylor(24)),
+    ('smooth-64x50-gravity-interface', WL.Workload(**{**WL.euler2d_smooth(64, seed=3502, ny=50).__dict__,
+                                                      'gravity': 0.7}))],
+    ids=['rt-24x96-interface', 'smooth-64x50-gravity-interface'])
+def test_source_with_interface_basis_matches_oracle_f64(name, w):
+    """The kernel variants that combine the source with the interface basis
+    (and with walls and fixed states for the Rayleigh-Taylor data)."""
+    s = solver(w, basis='interface')
+    p = oprob(w, basis='interface')
+    alpha = O.max_speed(p, w.U)
+    ref = O.rhs(p, w.U, w.V, w.W, alpha)
+    got = s.rhs(dev(w.U), dev(w.V), dev(w.W), dev(np.array(alpha)))
+    for k, (g, r) in enumerate(zip(got, ref)):
+        e = np.max(np.abs(host(g) - r)) / _scale(w, k, r)
+        print(f'  output {k}: rel err {e:.3e}')
+        assert e <= RTOL64, f'{name} output {k}: {e:.3e}'
+    # one step of the same variant
+    U, V, W = dev(w.U), dev(w.V), dev(w.W)
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    s.step(U, V, W, t, 1e9)
+    Uo, Vo, Wo, _ = O.step(p, w.U, w.V, w.W, O.time_step(p, alpha), (alpha, None, None))
+    for k, (g, r) in enumerate(zip((U, V, W), (Uo, Vo, Wo))):
+        e = np.max(np.abs(host(g) - r)) / np.max(np.abs(r))
+        print(f'  field {k}: rel err {e:.3e}')
+        assert e <= RTOL64
