@@ -72,6 +72,29 @@ template <typename T>
 __device__ __forceinline__ void st32(T* base, unsigned idx, T v) {
   *(T*)((char*)base + idx * (unsigned)sizeof(T)) = v;
 }
+// Asynchronous copy of kWave consecutive elements of one row (from column
+// col0, columns outside [0, nx) clamped to the edge) straight from global memory into
+// LDS (dst[0..kWave)), with no VGPR in between: each 4-byte load of a wave
+// writes lane i's word at byte 4i of its 256-byte part. The caller orders
+// it with LDS reads of dst: wait_copies() before reading the copy,
+// wait_lds_reads() after the last read of dst's previous contents.
+template <typename T>
+__device__ __forceinline__ void row_to_lds(const T* base, unsigned row_off, int col0, int nx, T* dst,
+                                           int lane) {
+  constexpr int P = sizeof(T) / 4;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int col = max(0, min(col0 + j * (kWave / P) + lane / P, nx - 1));
+    const unsigned byte = (row_off + (unsigned)col) * (unsigned)sizeof(T) + 4u * (unsigned)(lane % P);
+    __builtin_amdgcn_global_load_lds(
+        (const __attribute__((address_space(1))) void*)((const char*)base + byte),
+        (__attribute__((address_space(3))) void*)((char*)dst + 256 * j), 4, 0, 0);
+  }
+}
+// Waits that are also compiler barriers for memory accesses (the compiler's
+// own wait insertion does not order every LDS read after a pending copy)
+__device__ __forceinline__ void wait_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lds_reads() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -676,7 +699,8 @@ struct VjpArgs {
   const double* alpha;    // [2]; this pass uses alpha[dir]
   int dir;
   int add_identity;       // add the u-part of a_B (B's u-component is the identity)
-  T* G[3];                // outputs (u, along, other), overwritten
+  int accumulate;         // add the result to G (else overwrite G)
+  T* G[3];                // outputs (u, along, other)
   T* ghost;               // [rows][4][3][NC] contributions of virtual cells -2, -1, n, n+1
   int n, rows, plane;
   int bc_lo, bc_hi;
@@ -702,6 +726,16 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   const T h = T(A.h), ih = T(A.ih);
   const Scheme& s = A.s;
 
+  // with A.accumulate, the values this pass adds to, copied into LDS while
+  // the lane works
+  __shared__ T gin[NF][NC][kWave];
+  if (A.accumulate) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        row_to_lds(A.G[f], (unsigned)(c * A.plane + base), blockIdx.x * kXOut - 4, A.n, &gin[f][c][0], lane);
+  }
   T U[NC], Av[NC], Ov[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -836,11 +870,17 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     gA[c] += from_prev(tAp[c]) + from_next(tAm[c]);
     if (A.add_identity) gU[c] += aU[c];
   }
+  if (A.accumulate) wait_copies();
   if (out) {
     if (interior) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const unsigned idx = (unsigned)(c * A.plane + base + v);
+        if (A.accumulate) {
+          gU[c] += gin[0][c][lane];
+          gA[c] += gin[1][c][lane];
+          if (NF == 3) gO[c] += gin[NF - 1][c][lane];
+        }
         st32(A.G[0], idx, gU[c]);
         st32(A.G[1], idx, gA[c]);
         if (NF == 3) st32(A.G[2], idx, gO[c]);
@@ -867,7 +907,9 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
 // loaded): the interface cotangents of (r-1)+1/2, the reverse of cell r-1's
 // HWENO and face values if the strip owns it (contributions to rows r-2..r),
 // and the reverse of row r-2's pointwise fluxes; row r-2 is then complete up
-// to the halo terms and is added to G (which holds the x-direction result).
+// to the halo terms and is stored to G (the x-pass, which runs next, adds
+// its own result). The next row's inputs are copied into LDS while a row is
+// computed, so a row's loads wait on memory only once per strip.
 template <typename T>
 struct VjpYArgs {
   const T* X[3];          // u, v, w
@@ -878,13 +920,11 @@ struct VjpYArgs {
   int na;                 // number of a sets (1 or 3)
   const double* dt;
   const double* alpha;    // [2]; uses alpha[1]
-  T* G[3];                // in/out: u, v, w
+  T* G[3];                // out (overwritten): u, v, w
   T* ghost;               // [4][3][NC][nx]: rows -2, -1, ny, ny+1
   T* halo;                // [strip][2: to row o0-1, to row o1][2: u, w][NC][nx]
-  const T* xghost;        // x-pass ghost columns [ny][4][3][NC], folded here
   int nx, ny, rows, plane;
   int bc_lo, bc_hi;
-  int bcx_lo, bcx_hi;     // boundaries of the x-pass, whose ghost columns are folded here
   double gs[2][4];        // fixed ghost states of the low and high side (y)
   Scheme s;
 };
@@ -896,7 +936,6 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
   const int lane = threadIdx.x;
   const int x = blockIdx.x * kWave + lane;
   const bool colok = x < A.nx;
-  const int xc = colok ? x : A.nx - 1;
   const int o0 = -2 + blockIdx.y * A.rows;
   const int o1 = min(o0 + A.rows, A.ny + 2);
   const double dtv = A.dt ? *A.dt : 0.0;
@@ -906,31 +945,54 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
   const T cbt = T(A.cb * dtv);
   // interface cotangents (G, theta, xi) of the 3 previous interfaces, slot k mod 3
   __shared__ T lring[3][3][NC][kWave];
+  // the next row's inputs, copied in while the current row is computed:
+  // u, v, w, b_u, b_v, b_w, then the a_w sets
+  __shared__ T stage[9][NC][kWave];
+  const int col0 = blockIdx.x * kWave;
+  auto fetch = [&](int rr) {
+    const int g = map_index(rr, A.ny, A.bc_lo, A.bc_hi);
+    const bool in = rr >= 0 && rr < A.ny;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const unsigned off = (unsigned)(c * A.plane + g * A.nx);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) row_to_lds(A.X[f], off, col0, A.nx, &stage[f][c][0], lane);
+      if (in) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) row_to_lds(A.b[f], off, col0, A.nx, &stage[3 + f][c][0], lane);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (k < A.na) row_to_lds(A.aw[k], off, col0, A.nx, &stage[6 + k][c][0], lane);
+      }
+    }
+  };
   T Ua[NC], Ub[NC], Va[NC], Vb[NC], Wa[NC], Wb[NC];   // rows r-2, r-1
   T bU1[NC], bV1[NC], bW1[NC], aW1[NC];              // cotangents of row r-1
   T accUa[NC], accWa[NC], accUb[NC], accWb[NC];      // HWENO-reverse sums of rows r-2, r-1
 #pragma unroll
   for (int c = 0; c < NC; ++c) { accUa[c] = T(0); accWa[c] = T(0); accUb[c] = T(0); accWb[c] = T(0); }
-  // wavefronts holding column 0, 1, nx-2 or nx-1 fold the x-pass ghost columns
-  const bool xedge = blockIdx.x == 0 || (blockIdx.x + 1) * kWave >= A.nx - 1;
+  fetch(o0 - 2);
   for (int r = o0 - 2; r < o1 + 2; ++r) {
-    const int gr = map_index(r, A.ny, A.bc_lo, A.bc_hi);
     const bool inrow = r >= 0 && r < A.ny;
+    wait_copies();
     T Uc[NC], Vc[NC], Wc[NC], bUc[NC], bVc[NC], bWc[NC], aWc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const unsigned idx = (unsigned)(c * A.plane + gr * A.nx + xc);
-      Uc[c] = ld32(A.X[0], idx);
-      Vc[c] = ld32(A.X[1], idx);
-      Wc[c] = ld32(A.X[2], idx);
+      Uc[c] = stage[0][c][lane];
+      Vc[c] = stage[1][c][lane];
+      Wc[c] = stage[2][c][lane];
       bUc[c] = T(0); bVc[c] = T(0); bWc[c] = T(0); aWc[c] = T(0);
       if (inrow) {
-        bUc[c] = cbt * ld32(A.b[0], idx);
-        bVc[c] = cbt * ld32(A.b[1], idx);
-        bWc[c] = cbt * ld32(A.b[2], idx);
-        for (int k = 0; k < A.na; ++k) aWc[c] += T(A.ca[k]) * ld32(A.aw[k], idx);
+        bUc[c] = cbt * stage[3][c][lane];
+        bVc[c] = cbt * stage[4][c][lane];
+        bWc[c] = cbt * stage[5][c][lane];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (k < A.na) aWc[c] += T(A.ca[k]) * stage[6 + k][c][lane];
       }
     }
+    wait_lds_reads();
+    if (r + 1 < o1 + 2) fetch(r + 1);
     if constexpr (WALLS) {
       if (mirrored(r, A.ny, A.bc_lo, A.bc_hi)) {
         mirror_state<Sys, 1>(true, Uc);
@@ -1042,28 +1104,12 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
       prim_vjp(sy, Ua, q, bq, gU);
       if (colok) {
         if (o >= 0 && o < A.ny) {
-          // x-pass ghost columns of this row folded into their images
-          GhostImages xs{-1, -1, false, false};
-          if (xedge) xs = ghost_images(x, A.nx, A.bcx_lo, A.bcx_hi);
-          const T* xg = A.xghost + (size_t)o * 4 * 3 * NC;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const unsigned idx = (unsigned)(c * A.plane + o * A.nx + x);
-            T gx[3] = {ld32((const T*)A.G[0], idx), ld32((const T*)A.G[1], idx), ld32((const T*)A.G[2], idx)};
-            if (xs.a >= 0) {
-#pragma unroll
-              for (int f = 0; f < 3; ++f) {
-                const T ga = xg[xs.a * 3 * NC + f * NC + c];
-                gx[f] += WALLS && xs.flip_a && mirror_flips(0, f, c) ? -ga : ga;
-                if (xs.b >= 0) {
-                  const T gb = xg[xs.b * 3 * NC + f * NC + c];
-                  gx[f] += WALLS && xs.flip_b && mirror_flips(0, f, c) ? -gb : gb;
-                }
-              }
-            }
-            st32(A.G[0], idx, gx[0] + gU[c]);
-            st32(A.G[1], idx, gx[1] + gV[c]);
-            st32(A.G[2], idx, gx[2] + gW[c]);
+            st32(A.G[0], idx, gU[c]);
+            st32(A.G[1], idx, gV[c]);
+            st32(A.G[2], idx, gW[c]);
           }
         } else {
           const int slot = o < 0 ? o + 2 : o - A.ny + 2;
@@ -1606,69 +1652,7 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   constexpr int NC = Sys::NC;
   const Scheme sc = make_scheme(p);
   const int nx = p->nx, ny = p->ny, plane = nx * ny;
-  // x-pass
-  {
-    VjpArgs<T> A;
-    std::memset(&A, 0, sizeof(A));
-    for (int f = 0; f < 3; ++f) {
-      A.X[f] = X[f];
-      A.b[f] = (const T*)cot.b[f];
-    }
-    for (int k = 0; k < cot.na; ++k) {
-      A.a[k][0] = (const T*)cot.a[k][0];
-      A.a[k][1] = (const T*)cot.a[k][1];
-      A.ca[k] = cot.ca[k];
-    }
-    A.cb = cot.cb;
-    A.dt = dt;
-    A.alpha = alpha;
-    A.dir = 0;
-    A.add_identity = 1;
-    for (int f = 0; f < 3; ++f) A.G[f] = out[f];
-    A.ghost = (T*)wl.ghost;
-    A.n = nx;
-    A.rows = ny;
-    A.plane = plane;
-    A.bc_lo = p->bc[0];
-    A.bc_hi = p->bc[1];
-    for (int c = 0; c < 4; ++c) {
-      A.gs[0][c] = p->bc_state[0][c];
-      A.gs[1][c] = p->bc_state[1][c];
-    }
-    A.h = sc.dx;
-    A.ih = sc.idx;
-    A.s = sc;
-    dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
-    auto special = [](int b) { return b == HWENO_REFLECTIVE || b == HWENO_DIRICHLET; };
-    const bool xwalls = special(p->bc[0]) || special(p->bc[1]);
-    auto go = [&](auto walls) {
-      constexpr bool W = decltype(walls)::value;
-      if (cot.na == 1)
-        vjp_row_kernel<Sys, T, 0, DIM + 1, 1, W><<<grid, kWave, 0, st>>>(A, sy);
-      else
-        vjp_row_kernel<Sys, T, 0, DIM + 1, 3, W><<<grid, kWave, 0, st>>>(A, sy);
-    };
-    if (xwalls)
-      go(std::true_type{});
-    else
-      go(std::false_type{});
-    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    if constexpr (DIM == 1) {   // in 2D the y-pass folds these
-      const int tot = ny * g.nf * NC;
-      ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
-                                                             nx, ny, plane, NC, g.nf,
-                                                             p->bc[0], p->bc[1]);
-      if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    }
-  }
-  if constexpr (DIM == 2) {
-    if (Sys::kChar && NC == 4 && p->gravity != 0.0) {
-      source_vjp_kernel<T><<<(plane + 255) / 256, 256, 0, st>>>(
-          out[0], out[1], out[2], (const T*)cot.b[0], (const T*)cot.b[1], (const T*)cot.b[2], cot.cb,
-          dt, p->gravity, plane);
-      if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    }
-  }
+  // y-pass (2D): overwrites out, then folds its strip halos and ghost rows
   if constexpr (DIM == 2) {
     VjpYArgs<T> A;
     std::memset(&A, 0, sizeof(A));
@@ -1687,14 +1671,11 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     for (int f = 0; f < 3; ++f) A.G[f] = out[f];
     A.ghost = (T*)wl.ghost_y;
     A.halo = (T*)wl.halo;
-    A.xghost = (const T*)wl.ghost;
     A.nx = nx;
     A.ny = ny;
     A.plane = plane;
     A.bc_lo = p->bc[2];
     A.bc_hi = p->bc[3];
-    A.bcx_lo = p->bc[0];
-    A.bcx_hi = p->bc[1];
     for (int c = 0; c < 4; ++c) {
       A.gs[0][c] = p->bc_state[2][c];
       A.gs[1][c] = p->bc_state[3][c];
@@ -1724,6 +1705,71 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
         out[0], out[1], out[2], (T*)wl.ghost_y, (const T*)wl.halo, nx, ny, plane, NC, A.rows, nstrips,
         p->bc[2], p->bc[3]);
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+  }
+  // x-pass (in 2D after the y-pass, adding to its result), then the fold
+  // of its ghost columns
+  {
+    VjpArgs<T> A;
+    std::memset(&A, 0, sizeof(A));
+    for (int f = 0; f < 3; ++f) {
+      A.X[f] = X[f];
+      A.b[f] = (const T*)cot.b[f];
+    }
+    for (int k = 0; k < cot.na; ++k) {
+      A.a[k][0] = (const T*)cot.a[k][0];
+      A.a[k][1] = (const T*)cot.a[k][1];
+      A.ca[k] = cot.ca[k];
+    }
+    A.cb = cot.cb;
+    A.dt = dt;
+    A.alpha = alpha;
+    A.dir = 0;
+    A.add_identity = 1;
+    A.accumulate = DIM == 2;   // in 2D the y-pass has written out
+    for (int f = 0; f < 3; ++f) A.G[f] = out[f];
+    A.ghost = (T*)wl.ghost;
+    A.n = nx;
+    A.rows = ny;
+    A.plane = plane;
+    A.bc_lo = p->bc[0];
+    A.bc_hi = p->bc[1];
+    for (int c = 0; c < 4; ++c) {
+      A.gs[0][c] = p->bc_state[0][c];
+      A.gs[1][c] = p->bc_state[1][c];
+    }
+    A.h = sc.dx;
+    A.ih = sc.idx;
+    A.s = sc;
+    dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
+    auto special = [](int b) { return b == HWENO_REFLECTIVE || b == HWENO_DIRICHLET; };
+    const bool xwalls = special(p->bc[0]) || special(p->bc[1]);
+    auto go = [&](auto walls) {
+      constexpr bool W = decltype(walls)::value;
+      if (cot.na == 1)
+        vjp_row_kernel<Sys, T, 0, DIM + 1, 1, W><<<grid, kWave, 0, st>>>(A, sy);
+      else
+        vjp_row_kernel<Sys, T, 0, DIM + 1, 3, W><<<grid, kWave, 0, st>>>(A, sy);
+    };
+    if (xwalls)
+      go(std::true_type{});
+    else
+      go(std::false_type{});
+    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    {
+      const int tot = ny * g.nf * NC;
+      ghost_fold_kernel<T><<<(tot + 255) / 256, 256, 0, st>>>(out[0], out[1], out[2], (const T*)wl.ghost,
+                                                             nx, ny, plane, NC, g.nf,
+                                                             p->bc[0], p->bc[1]);
+      if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    }
+  }
+  if constexpr (DIM == 2) {
+    if (Sys::kChar && NC == 4 && p->gravity != 0.0) {
+      source_vjp_kernel<T><<<(plane + 255) / 256, 256, 0, st>>>(
+          out[0], out[1], out[2], (const T*)cot.b[0], (const T*)cot.b[1], (const T*)cot.b[2], cot.cb,
+          dt, p->gravity, plane);
+      if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    }
   }
   return HWENO_OK;
 }
