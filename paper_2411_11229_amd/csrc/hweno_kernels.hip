@@ -658,36 +658,12 @@ __global__ void ws_init_kernel(StepScalars* sc) {
 // state X = (u, a, o) -- a the derivative along the line, o the other one --
 // and cotangents a_B of B(X) = (u, a~, ...) and b of L(X), it writes
 //   G = (dB/dX)^T a_B + (dL_dir/dX)^T b
-// restricted to this direction's terms. Lanes hold "virtual" cells v =
+// restricted to this direction's terms (in 2D it adds that to G, which
+// holds the y-direction terms). Lanes hold "virtual" cells v =
 // 60 b - 4 + lane (ghost cells included), so every virtual cell in
 // [-2, n+2) is an output lane of exactly one block; contributions to ghost
 // cells go to a side buffer and are folded into their images by
 // ghost_fold_kernel (the transpose of the ghost index map).
-// The ghost cells whose image is cell x of a line of n cells: slots 0..3 are
-// the virtual cells -2, -1, n, n+1; a cell is the image of at most two of
-// them (a transmissive edge cell of both ghosts of its side), listed in slot
-// order, each with whether the reflective sign rules apply. Fixed-state
-// ghosts have no image (their values do not depend on the state).
-struct GhostImages {
-  int a, b;
-  bool flip_a, flip_b;
-};
-__device__ __forceinline__ GhostImages ghost_images(int x, int n, int lo, int hi) {
-  GhostImages g{-1, -1, false, false};
-  for (int k = 0; k < 4; ++k) {
-    const int v = k < 2 ? k - 2 : n + k - 2;
-    if (fixed_side(v, n, lo, hi) >= 0 || map_index(v, n, lo, hi) != x) continue;
-    if (g.a < 0) {
-      g.a = k;
-      g.flip_a = mirrored(v, n, lo, hi);
-    } else {
-      g.b = k;
-      g.flip_b = mirrored(v, n, lo, hi);
-    }
-  }
-  return g;
-}
-
 template <typename T>
 struct VjpArgs {
   const T* X[3];          // u, along-derivative, other derivative (null in 1D)
