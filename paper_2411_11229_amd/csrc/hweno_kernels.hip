@@ -675,8 +675,17 @@ struct VjpArgs {
   const double* alpha;    // [2]; this pass uses alpha[dir]
   int dir;
   int add_identity;       // add the u-part of a_B (B's u-component is the identity)
-  int accumulate;         // add the result to G (else overwrite G)
+  int accumulate;         // 2D: add the result and the y-pass's folds to G (else overwrite G)
   T* G[3];                // outputs (u, along, other)
+  // with accumulate: the y-pass's strip halos [strip][2 sides][u, w][NC][n]
+  // and ghost rows [4][3][NC][n], its strip height and count, the y sides
+  // ghost row k (-2, -1, ny, ny+1): the row it folds into (-1: none), whether
+  // the wall's sign rules apply, the strip (-1: none) and side of the halo
+  // term aimed at it
+  const T* yhalo;
+  const T* yghost;
+  int yR, ystrips;
+  int yimg[4], yflip[4], yqj[4], yqs[4];
   T* ghost;               // [rows][4][3][NC] contributions of virtual cells -2, -1, n, n+1
   int n, rows, plane;
   int bc_lo, bc_hi;
@@ -684,6 +693,27 @@ struct VjpArgs {
   double h, ih;
   Scheme s;
 };
+
+// The y-pass strip whose halo term is aimed at virtual row q: strip j (rows
+// [-2 + jR, -2 + (j+1)R)) sends side 0 to its row o0 - 1 and side 1 to its
+// row o1. Returns j (side in `side`), or -1.
+HWENO_HD int halo_source(int q, int R, int nstrips, int& side) {
+  if ((q + 3) % R == 0) {
+    const int j = (q + 3) / R;
+    if (j >= 1 && j <= nstrips - 1) {
+      side = 0;
+      return j;
+    }
+  }
+  if ((q + 2) % R == 0) {
+    const int j = (q + 2) / R - 1;
+    if (j >= 0 && j <= nstrips - 2) {
+      side = 1;
+      return j;
+    }
+  }
+  return -1;
+}
 
 template <class Sys, typename T, int D, int NF, int NA, bool WALLS>
 __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
@@ -702,15 +732,26 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   const T h = T(A.h), ih = T(A.ih);
   const Scheme& s = A.s;
 
-  // with A.accumulate, the values this pass adds to, copied into LDS while
-  // the lane works
+  // with A.accumulate, the values this pass adds to, and the y-pass halo
+  // term aimed at this row (u, w), copied into LDS while the lane works
   __shared__ T gin[NF][NC][kWave];
+  __shared__ T yh[2][NC][kWave];
+  int hside = 0;
+  const int hj = A.accumulate ? halo_source(row, A.yR, A.ystrips, hside) : -1;
   if (A.accumulate) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int f = 0; f < NF; ++f)
         row_to_lds(A.G[f], (unsigned)(c * A.plane + base), blockIdx.x * kXOut - 4, A.n, &gin[f][c][0], lane);
+    if (hj >= 0) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          row_to_lds(A.yhalo, (unsigned)(((hj * 4 + hside * 2 + hf) * NC + c) * A.n),
+                     blockIdx.x * kXOut - 4, A.n, &yh[hf][c][0], lane);
+    }
   }
   T U[NC], Av[NC], Ov[NC];
 #pragma unroll
@@ -846,7 +887,12 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     gA[c] += from_prev(tAp[c]) + from_next(tAm[c]);
     if (A.add_identity) gU[c] += aU[c];
   }
-  if (A.accumulate) wait_copies();
+  unsigned gmask = 0;   // y ghost rows folding into this row
+  if (A.accumulate) {
+    wait_copies();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gmask |= A.yimg[k] == row ? 1u << k : 0u;
+  }
   if (out) {
     if (interior) {
 #pragma unroll
@@ -856,6 +902,30 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
           gU[c] += gin[0][c][lane];
           gA[c] += gin[1][c][lane];
           if (NF == 3) gO[c] += gin[NF - 1][c][lane];
+          if (hj >= 0) {
+            gU[c] += yh[0][c][lane];
+            if (NF == 3) gO[c] += yh[1][c][lane];
+          }
+          // the y ghost rows whose image is this row (edge rows only), each
+          // with the halo term aimed at it, with the y walls' sign rules
+          if (gmask) {
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+              if (!((gmask >> k) & 1u)) continue;
+              const int qj = A.yqj[k], qs = A.yqs[k];
+              T gv[3];
+#pragma unroll
+              for (int f = 0; f < 3; ++f) {
+                gv[f] = A.yghost[((size_t)(k * 3 + f) * NC + c) * A.n + v];
+                if (qj >= 0 && f != 1)
+                  gv[f] += A.yhalo[((size_t)(qj * 4 + qs * 2 + (f == 0 ? 0 : 1)) * NC + c) * A.n + v];
+                if (A.yflip[k] && mirror_flips(1, f, c)) gv[f] = -gv[f];
+              }
+              gU[c] += gv[0];
+              gA[c] += gv[1];
+              if (NF == 3) gO[c] += gv[2];
+            }
+          }
         }
         st32(A.G[0], idx, gU[c]);
         st32(A.G[1], idx, gA[c]);
@@ -878,8 +948,8 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
 // transposes). Each lane owns one column and needs no neighbour lane. Strip k
 // owns the virtual rows [o0, o1) of [-2, ny+2) and reverses the HWENO of its
 // own cells only: the contributions of cell o0 to row o0-1 and of cell o1-1
-// to row o1 go to a halo buffer, and vjp_y_fold_kernel adds them (and the
-// ghost rows, kept in a side buffer) afterwards. At iteration r (row r
+// to row o1 go to a halo buffer, and the x-pass (vjp_row_kernel) adds them,
+// and the ghost rows kept in a side buffer, to the rows they belong to. At iteration r (row r
 // loaded): the interface cotangents of (r-1)+1/2, the reverse of cell r-1's
 // HWENO and face values if the strip owns it (contributions to rows r-2..r),
 // and the reverse of row r-2's pointwise fluxes; row r-2 is then complete up
@@ -1122,82 +1192,6 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
       hb[(2 * NC + c) * A.nx] = accUa[c];
       hb[(3 * NC + c) * A.nx] = accWa[c];
     }
-  }
-}
-
-// Completes vjp_y_kernel's result: adds the halo terms of the strip
-// boundaries and folds the ghost rows into the rows they were copied from.
-// Threads (boundary, column, field, component) add the two halo terms of a
-// boundary whose rows are both in [2, ny-3] (such rows belong to no other
-// boundary and to no ghost image); threads (last slot, column, field,
-// component) handle, in a fixed order, the boundaries near the edges (halo
-// terms aimed at ghost rows go into the ghost side buffer) and then the ghost
-// rows -2, -1, ny, ny+1, each into its image by the boundary's index map
-// (periodic: ny-2, ny-1, 0, 1; transmissive: 0, 0, ny-1, ny-1; reflective:
-// 1, 0, ny-1, ny-2 with the wall's sign rules; fixed states: none). Images
-// are always edge rows.
-// Strip k owns the virtual rows [-2 + k R, -2 + (k+1) R).
-template <typename T>
-__global__ __launch_bounds__(256) void vjp_y_fold_kernel(T* __restrict__ G0, T* __restrict__ G1,
-                                                         T* __restrict__ G2, T* __restrict__ ghost,
-                                                         const T* __restrict__ halo, int nx, int ny,
-                                                         int plane, int nc, int R, int nstrips,
-                                                         int lo, int hi) {
-  const long per = 3L * nc * nx;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= per * nstrips) return;
-  const int k = (int)(t / per);
-  const int rem = (int)(t - (long)k * per);
-  const int x = rem % nx;
-  const int fc = rem / nx;            // f * nc + c
-  const int f = fc / nc, c = fc % nc;
-  T* G = (f == 0 ? G0 : (f == 1 ? G1 : G2)) + (size_t)c * plane + x;
-  const int hf = f == 0 ? 0 : 1;      // halo field: u or w (v has no halo terms)
-  // halo term of strip j: side 0 -> its row o0-1, side 1 -> its row o1
-  auto hterm = [&](int j, int side) {
-    return halo[(((size_t)j * 4 + side * 2 + hf) * nc + c) * nx + x];
-  };
-  auto edge = [&](int v) { return v < 2 || v > ny - 3; };
-  if (k < nstrips - 1) {
-    // boundary between strips k and k+1: rows a = o1 - 1 (strip k), b = o1
-    const int o1 = -2 + (k + 1) * R;
-    if (f == 1 || edge(o1 - 1) || edge(o1)) return;
-    G[(size_t)(o1 - 1) * nx] += hterm(k + 1, 0);
-    G[(size_t)o1 * nx] += hterm(k, 1);
-    return;
-  }
-  // the edge thread of (column, field, component)
-  if (f != 1) {
-    auto add = [&](int v, T val) {
-      if (v >= 0 && v < ny) {
-        G[(size_t)v * nx] += val;
-      } else {
-        const int slot = v < 0 ? v + 2 : v - ny + 2;
-        ghost[((size_t)slot * 3 * nc + fc) * nx + x] += val;
-      }
-    };
-    // edge boundaries: o1 <= 2 at the bottom, o1 > ny - 3 at the top
-    int j = 0;
-    for (; j < nstrips - 1 && -2 + (j + 1) * R <= 2; ++j) {
-      const int o1 = -2 + (j + 1) * R;
-      add(o1 - 1, hterm(j + 1, 0));
-      add(o1, hterm(j, 1));
-    }
-    for (j = max(j, (ny - 1) / R); j < nstrips - 1; ++j) {
-      const int o1 = -2 + (j + 1) * R;
-      add(o1 - 1, hterm(j + 1, 0));
-      add(o1, hterm(j, 1));
-    }
-  }
-  const size_t gs = (size_t)3 * nc * nx;
-  const T* gp = ghost + (size_t)fc * nx + x;
-  const T gv[4] = {gp[0], gp[gs], gp[2 * gs], gp[3 * gs]};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {   // ghost rows -2, -1, ny, ny+1
-    const int v = k < 2 ? k - 2 : ny + k - 2;
-    if (fixed_side(v, ny, lo, hi) >= 0) continue;   // fixed states: no image
-    const bool neg = mirrored(v, ny, lo, hi) && mirror_flips(1, f, c);
-    G[(size_t)map_index(v, ny, lo, hi) * nx] += neg ? -gv[k] : gv[k];
   }
 }
 
@@ -1628,7 +1622,9 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   constexpr int NC = Sys::NC;
   const Scheme sc = make_scheme(p);
   const int nx = p->nx, ny = p->ny, plane = nx * ny;
-  // y-pass (2D): overwrites out, then folds its strip halos and ghost rows
+  // y-pass (2D): overwrites out; its strip halos and ghost rows are folded
+  // in by the x-pass
+  int ystrip_rows = 0, ystrips = 0;
   if constexpr (DIM == 2) {
     VjpYArgs<T> A;
     std::memset(&A, 0, sizeof(A));
@@ -1676,11 +1672,8 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     else
       go(vjp_y_kernel<Sys, T, false>, std::integral_constant<int, 4>{});
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
-    const long tot = 3L * NC * nx * nstrips;
-    vjp_y_fold_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
-        out[0], out[1], out[2], (T*)wl.ghost_y, (const T*)wl.halo, nx, ny, plane, NC, A.rows, nstrips,
-        p->bc[2], p->bc[3]);
-    if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
+    ystrip_rows = A.rows;
+    ystrips = nstrips;
   }
   // x-pass (in 2D after the y-pass, adding to its result), then the fold
   // of its ghost columns
@@ -1702,6 +1695,19 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     A.dir = 0;
     A.add_identity = 1;
     A.accumulate = DIM == 2;   // in 2D the y-pass has written out
+    if (DIM == 2) {
+      A.yhalo = (const T*)wl.halo;
+      A.yghost = (const T*)wl.ghost_y;
+      A.yR = ystrip_rows;
+      A.ystrips = ystrips;
+      for (int k = 0; k < 4; ++k) {
+        const int q = k < 2 ? k - 2 : ny + k - 2;
+        const bool fixed = fixed_side(q, ny, p->bc[2], p->bc[3]) >= 0;
+        A.yimg[k] = fixed ? -1 : map_index(q, ny, p->bc[2], p->bc[3]);
+        A.yflip[k] = mirrored(q, ny, p->bc[2], p->bc[3]);
+        A.yqj[k] = halo_source(q, ystrip_rows, ystrips, A.yqs[k]);
+      }
+    }
     for (int f = 0; f < 3; ++f) A.G[f] = out[f];
     A.ghost = (T*)wl.ghost;
     A.n = nx;
