@@ -337,8 +337,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f'bench.py: this build measures one GPU only (got --gpus {args.gpus}); '
-              'multi-GPU runs are not part of it.', file=sys.stderr)
+        print(f'bench.py: the solver runs on one GPU (got --gpus {args.gpus}); '
+              'there is no multi-GPU decomposition to measure.', file=sys.stderr)
         sys.exit(2)
     if args.probe == 'copy':
         copy_probe()
