@@ -287,6 +287,38 @@ def rayleigh_taylor_times():
     return out
 
 
+def launch_bound_times():
+    """Sizes where launch overhead sets the pace: the 1D Euler Riemann + sine
+    data (N = 2000, seeds 2000-2007, each to its T) and Example 4.11 at
+    60x240 to t = 1.95, FP64, stepped eagerly (five kernel launches per step)
+    and through HIP graphs of 32 steps (Solver.run(graph=True)); wall time
+    with inputs resident, after one warm-up run of each kind."""
+    import torch
+    from paper_2411_11229_amd import hweno, workloads
+    out = {}
+    cases = [(f'euler1d_riemann_2000_seed{sd}', workloads.euler1d_riemann_sine(2000, seed=sd))
+             for sd in range(2000, 2008)]
+    cases.append(('rayleigh_taylor_60x240', workloads.rayleigh_taylor(60)))
+    for name, w in cases:
+        s = hweno.Solver(hweno.Problem(**w.problem_kwargs()))
+        d = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device='cuda')
+        row = {}
+        for graph in (False, True):
+            s.run(d(w.U), d(w.V), d(w.W), t_end=w.t_end, max_steps=64, graph=graph)
+            U, V, W = d(w.U), d(w.V), d(w.W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n, t, _ = s.run(U, V, W, t_end=w.t_end, graph=graph)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            s.health()
+            row['graph' if graph else 'eager'] = dict(steps=n, t=t, wall_s=round(wall, 4),
+                                                      us_per_step=round(1e6 * wall / n, 2))
+        out[name] = row
+        print(json.dumps({name: row}), file=sys.stderr, flush=True)
+    return out
+
+
 def double_mach_time(nx=1600):
     """Example 4.7 at nx x nx/4 to t = 0.2, FP64 (five start-up steps at CFL
     0.1, then 0.6): wall time with inputs resident."""
@@ -330,6 +362,8 @@ def main():
                     help='compare the cell and interface characteristic bases instead')
     ap.add_argument('--double-mach', action='store_true',
                     help='time the double Mach reflection example at 1600x400 instead')
+    ap.add_argument('--launch-bound', action='store_true',
+                    help='eager vs HIP-graph stepping on launch-bound sizes (1D Euler, Example 4.11)')
     ap.add_argument('--rayleigh-taylor', action='store_true',
                     help='time the Rayleigh-Taylor example at the paper\'s meshes instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
@@ -359,6 +393,9 @@ def main():
         return
     if args.rayleigh_taylor:
         print(json.dumps({'rayleigh_taylor': rayleigh_taylor_times()}))
+        return
+    if args.launch_bound:
+        print(json.dumps({'launch_bound': launch_bound_times()}))
         return
 
     main_run = time_forward(args.n, args.precision, args.steps, args.warmup)
