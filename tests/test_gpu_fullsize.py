@@ -10,7 +10,8 @@ FP32, where the oracle cannot follow a whole run:
   a whole number of cells gives the rolled result: every cell runs the same
   arithmetic on the same values);
 * the FP32 run against the FP64 run (the FP64 path matches the oracle at
-  1e-12 on every smaller run), per field, reported and bounded.
+  1e-12 on every smaller run), per field, reported and bounded;
+and the largest grid one FP64 state array allows (11584^2), sampled.
 """
 import numpy as np
 import pytest
@@ -102,3 +103,78 @@ def test_smooth_1024_run_f32_against_f64():
         e = np.max(np.abs(host(b).astype(np.float64) - ref)) / np.max(np.abs(ref))
         print(f'  f32 vs f64 after {STEPS} steps: field {k} max rel err {e:.2e} (bound {lim:.0e})')
         assert e <= lim
+
+
+def _oracle_at_device(p, alpha, U, V, W, cells):
+    """The oracle operator at isolated cells, its two 5-cell lines per cell
+    read from device arrays (the arrays are too large to copy whole)."""
+    from test_gpu_parity import _mapidx
+    sy = O.make_system(p)
+    g, dl, eps = p.linear_gamma, p.linear_d, p.eps
+    out = []
+    for (j, i) in cells:
+        cols = torch.tensor([_mapidx(i + k, p.nx, p.bc[0], p.bc[1]) for k in range(-2, 3)], device='cuda')
+        rows = torch.tensor([_mapidx(j + k, p.ny, p.bc[2], p.bc[3]) for k in range(-2, 3)], device='cuda')
+        xl = lambda F: F[:, j, :].index_select(1, cols).double().cpu().numpy()
+        yl = lambda F: F[:, :, i].index_select(1, rows).double().cpu().numpy()
+        RUx, RVx, RWx, vt = O.sweep(sy, 0, xl(U), xl(V), xl(W), p.dx, alpha[0],
+                                    'transmissive', 'transmissive', g, dl, eps)
+        RUy, RWy, RVy, wt = O.sweep(sy, 1, yl(U), yl(W), yl(V), p.dy, alpha[1],
+                                    'transmissive', 'transmissive', g, dl, eps)
+        out.append((RUx[:, 2] + RUy[:, 2], RVx[:, 2] + RVy[:, 2], RWx[:, 2] + RWy[:, 2],
+                    vt[:, 2], wt[:, 2]))
+    return out
+
+
+def test_largest_state_array_sampled():
+    """The largest 2D Euler FP64 grid one state array allows (4 x 11584^2
+    doubles, 4.294e9 bytes, just under the 4 GiB the kernels address with
+    32-bit byte offsets), four-quadrant data built on the device: the
+    operator and the first stage at sampled cells (corners, the quadrant
+    junction, random cells, and the last rows and columns, whose offsets are
+    the largest) against the oracle evaluated cell by cell."""
+    n = 11584
+    assert 4 * n * n * 8 < 2 ** 32
+    print(f'case 2D Euler quadrants {n}x{n} FP64', flush=True)
+    small = WL.euler2d_quadrants(16, seed=4000)
+    kw = dict(small.problem_kwargs(), nx=n, ny=n, dx=1.0 / n, dy=1.0 / n)
+    p = O.Problem(**kw)
+    alpha = O.max_speed(O.Problem(**small.problem_kwargs()), small.U)   # the same four states
+    q = [torch.tensor(small.U[:, a, b], dtype=torch.float64, device='cuda')
+         for a, b in ((0, 0), (0, -1), (-1, 0), (-1, -1))]
+    xs = (torch.arange(n, device='cuda', dtype=torch.float64) + 0.5) / n
+    right = (xs >= 0.5).view(1, 1, n)
+    top = (xs >= 0.5).view(1, n, 1)
+    col = lambda k: q[k].view(4, 1, 1)
+    U = torch.where(top, torch.where(right, col(3), col(2)), torch.where(right, col(1), col(0))).contiguous()
+    V = torch.zeros_like(U)
+    W = torch.zeros_like(U)
+    from paper_2411_11229_amd import hweno
+    s = hweno.Solver(hweno.Problem(**kw))
+    cells = sample_cells(n, n, k=24, seed=13) + [(n - 1, n - 3), (n - 2, n - 1), (n - 3, 7), (n // 2, n - 2)]
+    ref = _oracle_at_device(p, alpha, U, V, W, cells)
+    got = s.rhs(U, V, W, dev(np.array(alpha)))
+    scale = [max(np.max(np.abs(r[k])) for r in ref) for k in range(5)]
+    for (j, i), r in zip(cells, ref):
+        for k in range(5):
+            e = np.max(np.abs(host(got[k][:, j, i]) - r[k]))
+            assert e <= RTOL64 * max(scale[k], 1.0), f'cell {(j, i)} output {k}: err {e:.3e}'
+    del got
+    torch.cuda.empty_cache()
+    stages = torch.empty(2 * 3 * 4 * n * n, dtype=torch.float64, device='cuda')
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dt_used = torch.zeros(1, dtype=torch.float64, device='cuda')
+    U0 = {c: host(U[:, j, i]) for c, (j, i) in enumerate(cells)}
+    s.step(U, V, W, t, 1e9, dt_used=dt_used, stages=stages)
+    dt = O.time_step(p, alpha, 'production', 0.6)
+    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-12)
+    X1 = stages[:3 * 4 * n * n].view(3, 4, n, n)
+    for c, ((j, i), r) in enumerate(zip(cells, ref)):
+        exp = (U0[c] + dt * r[0], r[3] + dt * r[1], r[4] + dt * r[2])
+        for k in range(3):
+            e = np.max(np.abs(host(X1[k][:, j, i]) - exp[k]))
+            assert e <= RTOL64 * max(np.max(np.abs(exp[k])), 1.0), f'stage 1 cell {(j, i)} field {k}: {e:.3e}'
+    s.health()
+    print(f'  {len(cells)} cells within 1e-12; dt {dt:.6e}')
+    del stages, U, V, W, s
+    torch.cuda.empty_cache()
