@@ -11,7 +11,8 @@ FP32, where the oracle cannot follow a whole run:
   arithmetic on the same values);
 * the FP32 run against the FP64 run (the FP64 path matches the oracle at
   1e-12 on every smaller run), per field, reported and bounded;
-and the largest grid one FP64 state array allows (11584^2), sampled.
+and the largest grid one FP64 state array allows (11584^2): the operator
+sampled, and the adjoint step by a dot-product test near the array ends.
 """
 import numpy as np
 import pytest
@@ -177,4 +178,72 @@ def test_largest_state_array_sampled():
     s.health()
     print(f'  {len(cells)} cells within 1e-12; dt {dt:.6e}')
     del stages, U, V, W, s
+    torch.cuda.empty_cache()
+
+
+def test_largest_state_array_adjoint_dot_product():
+    """The adjoint step at the largest FP64 grid (11584^2, periodic smooth
+    data built on the device) on cotangents and directions supported in the
+    last 48 rows only, where the byte offsets are the largest:
+    <(dX_{n+1}/dX_n)^T lam, delta> against Richardson central differences
+    <lam, (step(X + e delta) - step(X - e delta)) / 2e> of the frozen step."""
+    n = 11584
+    print(f'case 2D Euler smooth {n}x{n} FP64 adjoint', flush=True)
+    from paper_2411_11229_amd import hweno
+    g_, h = 1.4, 2.0 / n
+    kw = dict(dim=2, nx=n, ny=n, dx=h, dy=h, system='euler', gas_gamma=g_,
+              bc=('periodic',) * 4)
+    s = hweno.Solver(hweno.Problem(**kw))
+    x = (torch.arange(n, device='cuda', dtype=torch.float64) + 0.5) * h
+    X_, Y_ = x.view(1, n), x.view(n, 1)
+    pi = np.pi
+    sx, cx, sy_, cy = torch.sin(pi * X_), torch.cos(pi * X_), torch.sin(pi * Y_), torch.cos(pi * Y_)
+    rho = 1 + 0.2 * sx * sy_
+    u = 0.2 * cx * sy_
+    v = 0.2 * sx * cy
+    rx, ry = 0.2 * pi * cx * sy_, 0.2 * pi * sx * cy          # d rho / dx, dy
+    ux, uy = -0.2 * pi * sx * sy_, 0.2 * pi * cx * cy
+    vx, vy = 0.2 * pi * cx * cy, -0.2 * pi * sx * sy_
+    E = 1.0 / (g_ - 1) + 0.5 * rho * (u * u + v * v)
+
+    def cons_d(d_r, d_u, d_v):   # derivative of (rho, rho u, rho v, E) at p = 1
+        return torch.stack([d_r, d_r * u + rho * d_u, d_r * v + rho * d_v,
+                            0.5 * d_r * (u * u + v * v) + rho * (u * d_u + v * d_v)])
+    U = torch.stack([rho, rho * u, rho * v, E]).contiguous()
+    V = cons_d(rx, ux, vx).contiguous()
+    W = cons_d(ry, uy, vy).contiguous()
+    X = [U, V, W]
+    del sx, cx, sy_, cy, rho, u, v, rx, ry, ux, uy, vx, vy, E
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dt = torch.zeros(1, dtype=torch.float64, device='cuda')
+    rec = torch.zeros(6, dtype=torch.float64, device='cuda')
+    Y = [a.clone() for a in X]
+    s.step(Y[0], Y[1], Y[2], t, 1e9, dt_used=dt, alpha_rec=rec)
+    del Y
+    gen = torch.Generator(device='cuda').manual_seed(17)
+
+    def tail(a):   # random values in the last 48 rows, zero elsewhere
+        z = torch.zeros_like(a)
+        z[:, -48:, :] = torch.randn(z[:, -48:, :].shape, dtype=a.dtype, device='cuda', generator=gen)
+        return z
+    lam = [tail(a) for a in X]
+    delta = [tail(a) for a in X]
+    out = [torch.empty_like(a) for a in X]
+    s.adjoint_step(X[0], X[1], X[2], dt, rec, lam, out)
+    adj = sum(float((o * d).sum()) for o, d in zip(out, delta))
+    del out
+
+    def D(e):
+        acc = 0.0
+        for sign in (1.0, -1.0):
+            Z = [a + sign * e * d for a, d in zip(X, delta)]
+            s.step_frozen(Z[0], Z[1], Z[2], dt, rec)
+            acc += sign * sum(float((l * z).sum()) for l, z in zip(lam, Z))
+            del Z
+        return acc / (2 * e)
+    e = 1e-7
+    fd = (4 * D(e) - D(2 * e)) / 3
+    print(f'  adjoint {adj:.12e}  fd {fd:.12e}')
+    assert adj == pytest.approx(fd, rel=1e-6)
+    del X, lam, delta, s
     torch.cuda.empty_cache()
