@@ -16,7 +16,8 @@ import torch
 from oracle import hweno as O
 from paper_2411_11229_amd import workloads as WL
 
-from test_gpu_parity import RTOL64, check_run, dev, host, oprob, oracle_sensitivity, solver
+from test_gpu_parity import (RTOL64, check_run, dev, f32_bounds, host, oprob, oracle_sensitivity,
+                             solver)
 
 pytestmark = pytest.mark.gpu
 R3 = math.sqrt(3.0)
@@ -54,6 +55,26 @@ def test_split_rhs_matches_oracle_f64(name, w):
         e = np.max(np.abs(host(g) - r)) / _scale(w, k, r)
         print(f'  output {k}: rel err {e:.3e}')
         assert e <= RTOL64, f'{name} output {k}: {e:.3e}'
+
+
+@pytest.mark.parametrize("name,w", [cases()[0], cases()[2]], ids=[cases()[k][0] for k in (0, 2)])
+def test_split_rhs_f32(name, w):
+    """The FP32 form with split sides against the FP64 oracle on the same
+    (FP32-rounded) data, within the derived FP32 bounds."""
+    print(f'case {name} f32', flush=True)
+    for k in ('U', 'V', 'W'):
+        setattr(w, k, getattr(w, k).astype(np.float32).astype(np.float64))
+    s = solver(w, precision='f32')
+    p = oprob(w)
+    alpha = O.max_speed(p, w.U)
+    f32 = lambda a: dev(a, torch.float32)
+    got = s.rhs(f32(w.U), f32(w.V), f32(w.W), dev(np.array(alpha)))
+    ref = O.rhs(p, w.U, w.V, w.W, alpha)
+    tol = f32_bounds(w, alpha)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = np.max(np.abs(host(g) - r))
+        print(f'  output {k}: abs err {err:.3e}  bound {tol[k]:.3e}')
+        assert err <= tol[k], f'output {k}: abs err {err:.3e} > bound {tol[k]:.3e}'
 
 
 def _steps(s, U, V, W, n, t_end=1e9):
