@@ -235,8 +235,9 @@ hweno_status hweno_step_frozen(const hweno_problem* prob, void* u, void* v, void
  * (in the workspace, which also holds lambda2 and lambda1). At the kinks of
  * |beta0 - beta_k| the derivative of |.| is taken as sign(0) = 0. Output
  * buffers must not alias any input. The result is deterministic: every sum
- * is formed in a fixed order, without atomics. Returns HWENO_EUNSUPPORTED
- * for the Euler systems with the interface basis and for split sides.
+ * is formed in a fixed order, without atomics. With the interface basis
+ * the basis of each face's Roe matrix is differentiated with respect to
+ * both cells that define it. Returns HWENO_EUNSUPPORTED for split sides.
  */
 hweno_status hweno_adjoint_step(const hweno_problem* prob, const void* u_n, const void* v_n,
                                 const void* w_n, const void* stages, const double* dt,

@@ -632,6 +632,151 @@ HWENO_HD void hweno_cell_vjp(const Sys& sy, const Scheme& s, double h, double ih
   }
 }
 
+// Reverse of Euler::roe_eig (the basis of Roe's matrix of UL, UR): the
+// basis cotangent eb -> contributions to both states. Forward: r = rho^-1/2,
+// a = 1/(rho_L r_L + rho_R r_R), m = U_1 r, n = U_2 r, p = (g-1)(U_E - (m^2 +
+// n^2)/2), X = U_E + p; mu = (m_L + m_R) a, nu = (n_L + n_R) a, H = (X_L r_L
+// + X_R r_R) a, k = (mu^2 + nu^2)/2, c2 = (g-1)(H - k), ic = c2^-1/2,
+// c = c2 ic, b1 = (g-1) ic^2, b2 = b1 k.
+template <int DIM, typename T>
+HWENO_HD void roe_eig_vjp(const Euler<DIM>& sy, const T (&UL)[DIM + 2], const T (&UR)[DIM + 2],
+                          const typename Euler<DIM>::template Eig<T>& e, EigBar<T> eb,
+                          T (&gUL)[DIM + 2], T (&gUR)[DIM + 2]) {
+  constexpr int E = DIM + 1;
+  const T gm1 = T(sy.gas - 1.0);
+  const T rl = rsqrt_nr(UL[0]), rr = rsqrt_nr(UR[0]);
+  const T a = rcp_nr(UL[0] * rl + UR[0] * rr);
+  const T ml = UL[1] * rl, mr = UR[1] * rr;
+  const T nl = DIM == 2 ? UL[2] * rl : T(0), nr = DIM == 2 ? UR[2] * rr : T(0);
+  const T XL = UL[E] + gm1 * (UL[E] - T(0.5) * (ml * ml + nl * nl));
+  const T XR = UR[E] + gm1 * (UR[E] - T(0.5) * (mr * mr + nr * nr));
+  const T c2 = gm1 * (e.H - e.k);
+  eb.b1 += e.k * eb.b2;
+  eb.k += e.b1 * eb.b2;
+  eb.ic += T(2) * gm1 * e.ic * eb.b1;
+  T gc2 = e.ic * eb.c;
+  eb.ic += c2 * eb.c;
+  gc2 += T(-0.5) * e.ic * e.ic * e.ic * eb.ic;
+  eb.H += gm1 * gc2;
+  eb.k -= gm1 * gc2;
+  eb.mu += e.mu * eb.k;
+  eb.nu += e.nu * eb.k;
+  const T ga = (ml + mr) * eb.mu + (nl + nr) * eb.nu + (XL * rl + XR * rr) * eb.H;
+  T gml = a * eb.mu, gmr = a * eb.mu;
+  T gnl = a * eb.nu, gnr = a * eb.nu;
+  const T gXL = rl * a * eb.H, gXR = rr * a * eb.H;
+  T grl = XL * a * eb.H, grr = XR * a * eb.H;
+  gUL[E] += (T(1) + gm1) * gXL;
+  gml -= gm1 * ml * gXL;
+  gnl -= gm1 * nl * gXL;
+  gUR[E] += (T(1) + gm1) * gXR;
+  gmr -= gm1 * mr * gXR;
+  gnr -= gm1 * nr * gXR;
+  gUL[1] += rl * gml;
+  grl += UL[1] * gml;
+  gUR[1] += rr * gmr;
+  grr += UR[1] * gmr;
+  if constexpr (DIM == 2) {
+    gUL[2] += rl * gnl;
+    grl += UL[2] * gnl;
+    gUR[2] += rr * gnr;
+    grr += UR[2] * gnr;
+  }
+  const T gS = -a * a * ga;
+  gUL[0] += rl * gS;
+  grl += UL[0] * gS;
+  gUR[0] += rr * gS;
+  grr += UR[0] * gS;
+  gUL[0] += T(-0.5) * rl * rl * rl * grl;
+  gUR[0] += T(-0.5) * rr * rr * rr * grr;
+}
+
+// Reverse of hweno_cell_iface<D> (the interface-basis switch): the right-face
+// value in the basis of Roe's matrix of (U0, Up), the left-face value in that
+// of (Um, U0), v~ in the cell basis; each application is reversed with its
+// basis, whose cotangent goes to the states that define it.
+template <int D, class Sys, typename T>
+HWENO_HD void hweno_cell_iface_vjp(const Sys& sy, const Scheme& s, double h, double ih,
+                                   const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
+                                   const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
+                                   const T (&Ap)[Sys::NC], const T (&guR)[Sys::NC],
+                                   const T (&guL)[Sys::NC], const T (&gat)[Sys::NC],
+                                   T (&gUm)[Sys::NC], T (&gU0)[Sys::NC], T (&gUp)[Sys::NC],
+                                   T (&gAm)[Sys::NC], T (&gAp)[Sys::NC]) {
+  constexpr int NC = Sys::NC;
+  if constexpr (!Sys::kChar) {
+    hweno_cell_vjp<D>(sy, s, h, ih, Um, U0, Up, Am, Ap, guR, guL, gat, gUm, gU0, gUp, gAm, gAp);
+  } else {
+    auto apply = [&](const auto& e, int which, const T (&gout)[NC], EigBar<T>& eb) {
+      T wm[NC], w0[NC], wp[NC], am[NC], ap[NC], c[NC];
+      sy.template project<D>(e, Um, wm);
+      sy.template project<D>(e, U0, w0);
+      sy.template project<D>(e, Up, wp);
+      sy.template project<D>(e, Am, am);
+      sy.template project<D>(e, Ap, ap);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        T r_, l_, t_;
+        hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, r_, l_, t_);
+        c[j] = which == 0 ? r_ : (which == 1 ? l_ : t_);
+      }
+      T gc[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) gc[j] = T(0);
+      unproject_vjp<D>(sy, e, c, gout, eb, gc);
+      T gwm[NC], gw0[NC], gwp[NC], gam[NC], gap[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0); gam[j] = T(0); gap[j] = T(0);
+        hweno_point_vjp<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih,
+                           which == 0 ? (double)gc[j] : 0.0, which == 1 ? (double)gc[j] : 0.0,
+                           which == 2 ? (double)gc[j] : 0.0, gwm[j], gw0[j], gwp[j], gam[j], gap[j]);
+      }
+      project_vjp<D>(sy, e, Um, gwm, eb, gUm);
+      project_vjp<D>(sy, e, U0, gw0, eb, gU0);
+      project_vjp<D>(sy, e, Up, gwp, eb, gUp);
+      project_vjp<D>(sy, e, Am, gam, eb, gAm);
+      project_vjp<D>(sy, e, Ap, gap, eb, gAp);
+    };
+    {
+      const auto e = sy.roe_eig(U0, Up);
+      EigBar<T> eb;
+      apply(e, 0, guR, eb);
+      roe_eig_vjp(sy, U0, Up, e, eb, gU0, gUp);
+    }
+    {
+      const auto e = sy.roe_eig(Um, U0);
+      EigBar<T> eb;
+      apply(e, 1, guL, eb);
+      roe_eig_vjp(sy, Um, U0, e, eb, gUm, gU0);
+    }
+    {
+      const auto q = sy.prim(U0);
+      const auto e = sy.eig(q);
+      EigBar<T> eb;
+      apply(e, 2, gat, eb);
+      PrimBar<T> pb;
+      eig_vjp(sy, q, e, eb, pb);
+      prim_vjp(sy, U0, q, pb, gU0);
+    }
+  }
+}
+
+// Either basis, by template flag.
+template <int D, bool IFACE, bool kFused = false, class Sys, typename T>
+HWENO_HD void hweno_cell_vjp_b(const Sys& sy, const Scheme& s, double h, double ih,
+                               const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
+                               const T (&Up)[Sys::NC], const T (&Am)[Sys::NC],
+                               const T (&Ap)[Sys::NC], const T (&guR)[Sys::NC],
+                               const T (&guL)[Sys::NC], const T (&gat)[Sys::NC],
+                               T (&gUm)[Sys::NC], T (&gU0)[Sys::NC], T (&gUp)[Sys::NC],
+                               T (&gAm)[Sys::NC], T (&gAp)[Sys::NC]) {
+  if constexpr (IFACE)
+    hweno_cell_iface_vjp<D>(sy, s, h, ih, Um, U0, Up, Am, Ap, guR, guL, gat, gUm, gU0, gUp, gAm, gAp);
+  else
+    hweno_cell_vjp<D, kFused>(sy, s, h, ih, Um, U0, Up, Am, Ap, guR, guL, gat, gUm, gU0, gUp, gAm, gAp);
+}
+
 // Reverse of central_corr (linear): interface cotangents (gDf, gDh) ->
 // contributions to f_{i-1..i+2}, h_{i-1}, h_{i+2}.
 template <typename T>

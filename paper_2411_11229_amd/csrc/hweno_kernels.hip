@@ -717,7 +717,7 @@ HWENO_HD int halo_source(int q, int R, int nstrips, int& side) {
   return -1;
 }
 
-template <class Sys, typename T, int D, int NF, int NA, bool WALLS>
+template <class Sys, typename T, int D, int NF, int NA, bool WALLS, bool IFACE = false>
 __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   // WALLS: some side of this direction is reflective or fixed
   constexpr int NC = Sys::NC;
@@ -807,7 +807,7 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     Ap[c] = from_next(Av[c]);
   }
   T uR[NC], uL[NC], at_[NC], vR[NC], vL[NC];
-  hweno_cell<D>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, uR, uL, at_);
+  hweno_cell_b<D, IFACE>(sy, s, A.h, A.ih, sy.prim(U), Um, U, Up, Am, Ap, uR, uL, at_);
 #pragma unroll
   for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Am[c], Ap[c], ih, vR[c], vL[c]);
   // ---- interface cotangents: L_i = -(F_{i+1/2} - F_{i-1/2}) / h
@@ -881,7 +881,8 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     tm[c] = T(0); tc[c] = T(0); tp[c] = T(0); tAm[c] = T(0); tAp[c] = T(0);
     face_derivs_vjp(gvR[c], gvL[c], ih, tm[c], tc[c], tp[c], tAm[c], tAp[c]);
   }
-  hweno_cell_vjp<D, true>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, guR, guL, aA, tm, tc, tp, tAm, tAp);
+  hweno_cell_vjp_b<D, IFACE, true>(sy, s, A.h, A.ih, Um, U, Up, Am, Ap, guR, guL, aA, tm, tc, tp,
+                                   tAm, tAp);
   // ---- gather: own + right-neighbour part of the left lane + left part of the right lane
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -977,7 +978,7 @@ struct VjpYArgs {
   Scheme s;
 };
 
-template <class Sys, typename T, bool WALLS>
+template <class Sys, typename T, bool WALLS, bool IFACE = false>
 __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   using Bar = typename BarOf<Sys, T>::type;
@@ -1075,7 +1076,7 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
       // reverse of cell r-1's faces: top face -> interface (r-1)+1/2 (minus
       // side), bottom face -> interface (r-2)+1/2 (plus side)
       T uT[NC], uB[NC], wt_[NC], wT[NC], wB[NC];
-      hweno_cell<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, uT, uB, wt_);
+      hweno_cell_b<1, IFACE>(sy, s, s.dy, s.idy, sy.prim(Ub), Ua, Ub, Uc, Wa, Wc, uT, uB, wt_);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_derivs(Ua[c], Ub[c], Uc[c], Wa[c], Wc[c], ih, wT[c], wB[c]);
       T hG[NC], hT[NC], pG[NC], pT[NC], guT[NC], gwT[NC], guB[NC], gwB[NC];
@@ -1108,8 +1109,8 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
         tm[c] = T(0); tc[c] = T(0); tWm[c] = T(0);
         face_derivs_vjp(gwT[c], gwB[c], ih, tm[c], tc[c], accUc[c], tWm[c], accWc[c]);
       }
-      hweno_cell_vjp<1>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, guT, guB, aW1, tm, tc, accUc, tWm,
-                        accWc);
+      hweno_cell_vjp_b<1, IFACE>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, guT, guB, aW1, tm, tc,
+                                 accUc, tWm, accWc);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         accUa[c] += tm[c];
@@ -1624,6 +1625,8 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   constexpr int NC = Sys::NC;
   const Scheme sc = make_scheme(p);
   const int nx = p->nx, ny = p->ny, plane = nx * ny;
+  // the interface basis changes only the per-cell reverse (three bases)
+  const bool iface = Sys::kChar && p->char_basis == HWENO_BASIS_INTERFACE;
   // y-pass (2D): overwrites out; its strip halos and ghost rows are folded
   // in by the x-pass
   int ystrip_rows = 0, ystrips = 0;
@@ -1669,10 +1672,18 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
       dim3 grid((nx + kWave - 1) / kWave, nstrips);
       kernel<<<grid, kWave, 0, st>>>(A, sy);
     };
-    if (walls)
+    if (iface) {
+      if constexpr (Sys::kChar) {
+        if (walls)
+          go(vjp_y_kernel<Sys, T, true, true>, std::integral_constant<int, 20>{});
+        else
+          go(vjp_y_kernel<Sys, T, false, true>, std::integral_constant<int, 4>{});
+      }
+    } else if (walls) {
       go(vjp_y_kernel<Sys, T, true>, std::integral_constant<int, 20>{});
-    else
+    } else {
       go(vjp_y_kernel<Sys, T, false>, std::integral_constant<int, 4>{});
+    }
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     ystrip_rows = A.rows;
     ystrips = nstrips;
@@ -1727,17 +1738,27 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
     dim3 grid((nx + 4 + kXOut - 1) / kXOut, ny);
     auto special = [](int b) { return b == HWENO_REFLECTIVE || b == HWENO_DIRICHLET; };
     const bool xwalls = special(p->bc[0]) || special(p->bc[1]);
-    auto go = [&](auto walls) {
-      constexpr bool W = decltype(walls)::value;
+    auto go = [&](auto walls, auto ifc) {
+      constexpr bool W = decltype(walls)::value, I = decltype(ifc)::value;
       if (cot.na == 1)
-        vjp_row_kernel<Sys, T, 0, DIM + 1, 1, W><<<grid, kWave, 0, st>>>(A, sy);
+        vjp_row_kernel<Sys, T, 0, DIM + 1, 1, W, I><<<grid, kWave, 0, st>>>(A, sy);
       else
-        vjp_row_kernel<Sys, T, 0, DIM + 1, 3, W><<<grid, kWave, 0, st>>>(A, sy);
+        vjp_row_kernel<Sys, T, 0, DIM + 1, 3, W, I><<<grid, kWave, 0, st>>>(A, sy);
     };
-    if (xwalls)
-      go(std::true_type{});
-    else
-      go(std::false_type{});
+    auto go_w = [&](auto ifc) {
+      if (xwalls)
+        go(std::true_type{}, ifc);
+      else
+        go(std::false_type{}, ifc);
+    };
+    if constexpr (Sys::kChar) {
+      if (iface)
+        go_w(std::true_type{});
+      else
+        go_w(std::false_type{});
+    } else {
+      go_w(std::false_type{});
+    }
     if (check_launch() != HWENO_OK) return HWENO_EDEVICE;
     {
       const int tot = ny * g.nf * NC;
@@ -1997,7 +2018,6 @@ hweno_status hweno_adjoint_step(const hweno_problem* p, const void* u_n, const v
   const bool two = p->dim == 2;
   if (!u_n || !v_n || !dt || !alpha_rec || !lam_u_in || !lam_v_in || !lam_u_out || !lam_v_out || !ws)
     return HWENO_EINVAL;
-  if (p->system == HWENO_EULER && p->char_basis == HWENO_BASIS_INTERFACE) return HWENO_EUNSUPPORTED;
   if (has_split(p)) return HWENO_EUNSUPPORTED;
   if (two && (!w_n || !lam_w_in || !lam_w_out)) return HWENO_EINVAL;
   if (!two && (w_n || lam_w_in || lam_w_out)) return HWENO_EINVAL;

@@ -10,6 +10,8 @@
   against the FP64 oracle's reverse-mode gradient (torch-CPU, same source as
   the NumPy oracle, with its own recorded alphas and time steps), element by
   element (1e-8 of each field's max in FP64; FP32 reported and bounded).
+* Both characteristic bases: the cell basis, and the interface basis, whose
+  Roe-matrix bases depend on both cells of each face (cases '-interface').
 * Full size of the adjoint workload (512^2, 200 steps, checkpoints every 20):
   16 random directions against finite differences of GPU rollouts.
 """
@@ -33,9 +35,9 @@ def R():
     return rollout
 
 
-def solver(w, precision='f64'):
+def solver(w, precision='f64', **kw):
     h = H()
-    return h.Solver(h.Problem(**w.problem_kwargs(), precision=precision))
+    return h.Solver(h.Problem(**w.problem_kwargs(), precision=precision, **kw))
 
 
 def dev(a, dtype=torch.float64):
@@ -70,14 +72,27 @@ def cases():
         w.W = w.W * 0.5 + 0.1
         return w
     out.append(('advection2d', adv2d))
+    # the interface basis (face values in the basis of each face's Roe matrix)
+    out += [('euler1d-riemann-interface', lambda: WL.euler1d_riemann_sine(130, seed=2009)),
+            ('euler2d-quadrants-interface', lambda: WL.euler2d_quadrants(48, seed=4105, ny=66)),
+            ('euler2d-reflective-interface',
+             lambda: WL.with_bc(WL.euler2d_smooth(61, seed=3105, ny=37), ('reflective',) * 4))]
     return out
+
+
+def options(name):
+    """Problem options a case adds to its workload's."""
+    return dict(basis='interface') if name.endswith('-interface') else {}
 
 
 # Cases whose map is curved enough that the extrapolated differences need a
 # smaller step (walls next to piecewise-constant data: the oracle's own
 # reverse-mode gradient and its differences differ by 1.7e-5 at 1e-7 there,
 # by 6e-8 at 1e-8).
-FD_STEP = {'euler2d-mixed-walls': 1e-8}
+# The interface basis next to walls on smooth data likewise: the extrapolated
+# differences there approach the adjoint as 8e-4, 2e-5, 1.1e-6, 4e-8, 2e-8
+# (relative) for steps of 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, then rounding grows.
+FD_STEP = {'euler2d-mixed-walls': 1e-8, 'euler2d-reflective-interface': 1e-8}
 
 
 def state(w, dtype=torch.float64):
@@ -94,7 +109,7 @@ def frozen_map(s, X, dt, rec):
 def test_adjoint_step_matches_finite_differences(name, mk):
     print(f'case {name}', flush=True)
     w = mk()
-    s = solver(w)
+    s = solver(w, **options(name))
     X = state(w)
     two = len(X) == 3
     # record a step's dt and stage alphas
@@ -140,8 +155,8 @@ def test_adjoint_step_matches_finite_differences(name, mk):
     assert adj == pytest.approx(fd, rel=1e-6, abs=1e-9 * sum(float(l.abs().sum()) for l in lam))
 
 
-def _oracle_grad(w, steps, target):
-    p = O.Problem(**w.problem_kwargs())
+def _oracle_grad(w, steps, target, **kw):
+    p = O.Problem(**w.problem_kwargs(), **kw)
     _, _, _, log = O.run(p, w.U, w.V, w.W, 1e9, max_steps=steps)
     t = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, requires_grad=True)
     U, V, W = t(w.U), t(w.V), t(w.W)
@@ -151,8 +166,8 @@ def _oracle_grad(w, steps, target):
     return [x.grad.numpy() for x in (U, V, W) if x is not None], float(J)
 
 
-def _gpu_grad(w, steps, target, precision='f64', every=4):
-    s = solver(w, precision)
+def _gpu_grad(w, steps, target, precision='f64', every=4, **kw):
+    s = solver(w, precision, **kw)
     dt_ = torch.float64 if precision == 'f64' else torch.float32
     X = [x.requires_grad_(True) for x in state(w, dt_)]
     two = len(X) == 3
@@ -173,7 +188,12 @@ ROLL = [('euler2d-smooth', lambda: WL.euler2d_smooth(24, seed=3102, ny=20), 6),
                                                   ('reflective', 'transmissive', 'reflective', 'reflective')), 5),
         ('euler2d-mixed-walls', lambda: WL.with_bc(WL.euler2d_quadrants(21, seed=4104, ny=18),
                                                    ('transmissive', 'reflective', 'reflective',
-                                                    'transmissive')), 4)]
+                                                    'transmissive')), 4),
+        ('euler1d-riemann-interface', lambda: WL.euler1d_riemann_sine(64, seed=2010), 9),
+        ('euler2d-quadrants-interface', lambda: WL.euler2d_quadrants(20, seed=4106, ny=18), 5),
+        ('euler2d-reflective-interface', lambda: WL.with_bc(WL.euler2d_smooth(22, seed=3106, ny=19),
+                                                            ('reflective', 'transmissive',
+                                                             'reflective', 'reflective')), 5)]
 
 
 @pytest.mark.parametrize("name,mk,steps", ROLL, ids=[c[0] for c in ROLL])
@@ -182,15 +202,16 @@ def test_rollout_gradient_matches_oracle(name, mk, steps):
     w = mk()
     rng = np.random.default_rng(11)
     target = w.U + 0.05 * rng.standard_normal(w.U.shape)
-    go, Jo = _oracle_grad(w, steps, target)
-    gg, Jg = _gpu_grad(w, steps, target)
+    kw = options(name)
+    go, Jo = _oracle_grad(w, steps, target, **kw)
+    gg, Jg = _gpu_grad(w, steps, target, **kw)
     assert Jg == pytest.approx(Jo, rel=1e-10)
     for k, (a, b) in enumerate(zip(gg, go)):
         err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
         print(f'  field {k}: rel err {err:.3e}')
         assert err <= 1e-8, f'field {k}: {err:.3e}'
     # FP32 forward and adjoint against the FP64 oracle gradient
-    g32, J32 = _gpu_grad(w, steps, target, precision='f32')
+    g32, J32 = _gpu_grad(w, steps, target, precision='f32', **kw)
     for k, (a, b) in enumerate(zip(g32, go)):
         err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
         print(f'  fp32 field {k}: rel err {err:.3e}')

@@ -1,8 +1,8 @@
 """The interface-basis switch (Jiang and Shu's characteristic decomposition:
 face values in the eigenvectors of Roe's matrix of the two cells sharing the
 face, the modified derivative in the cell basis) on the HIP path against the
-FP64 oracle, with the tolerances of the cell-basis parity tests; and the
-adjoint's refusal of it."""
+FP64 oracle, with the tolerances of the cell-basis parity tests. Its adjoint
+is tested with the other adjoint cases (names ending in '-interface')."""
 import numpy as np
 import pytest
 import torch
@@ -135,16 +135,3 @@ def test_interface_basis_run_matches_oracle(name, w, steps):
     print(f'  dt rel err {e:.3e}  oracle 1-ulp divergence {dt_div:.3e}')
     assert e <= max(10 * dt_div, 1e-12)
     s.health()
-
-
-def test_adjoint_rejects_interface_basis():
-    from paper_2411_11229_amd import hweno
-    w = WL.euler2d_smooth(16, seed=3304, ny=12)
-    s = solver(w, **IF)
-    X = [dev(w.U), dev(w.V), dev(w.W)]
-    dt = torch.full((1,), 1e-3, dtype=torch.float64, device='cuda')
-    rec = torch.ones(6, dtype=torch.float64, device='cuda')
-    out = [torch.empty_like(x) for x in X]
-    with pytest.raises(hweno.HwenoError) as ei:
-        s.adjoint_step(X[0], X[1], X[2], dt, rec, [x.clone() for x in X], out)
-    assert ei.value.code == -2

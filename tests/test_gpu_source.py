@@ -142,15 +142,23 @@ ADJ = [('rt-12x48', lambda: WL.rayleigh_taylor(12)),
                                                   cons(0.7, 0.1, 0.2, 1.2)))),
        ('euler1d-dirichlet', lambda: dirichlet(WL.euler1d_riemann_sine(90, seed=2502),
                                                ('transmissive', 'dirichlet', 'periodic', 'periodic'),
-                                               (None, (0.8, -0.3, 2.5), None, None)))]
+                                               (None, (0.8, -0.3, 2.5), None, None))),
+       # the interface basis with the source, fixed states and walls
+       ('rt-12x48-interface', lambda: WL.rayleigh_taylor(12)),
+       ('quadrants-dirichlet-interface',
+        lambda: dirichlet(WL.euler2d_quadrants(70, seed=4503, ny=40),
+                          ('dirichlet', 'transmissive', 'reflective', 'dirichlet'),
+                          (cons(1.0, 0.3, -0.2, 2.0), None, None, cons(0.7, 0.1, 0.2, 1.2))))]
 
 
 @pytest.mark.parametrize("name,mk", ADJ, ids=[a[0] for a in ADJ])
 def test_adjoint_step_with_source_and_fixed_states(name, mk):
     """One adjoint step against the oracle's reverse mode of the same frozen
     step (the dt and stage alphas the GPU recorded), element by element."""
+    print(f'case {name}', flush=True)
     w = mk()
-    s = solver(w)
+    kw = dict(basis='interface') if name.endswith('-interface') else {}
+    s = solver(w, **kw)
     X = state(w)
     two = len(X) == 3
     Y = [x.clone() for x in X]
@@ -163,7 +171,7 @@ def test_adjoint_step_with_source_and_fixed_states(name, mk):
     out = [torch.empty_like(x) for x in X]
     s.adjoint_step(X[0], X[1], X[2] if two else None, dt, rec, lam, out)
     # oracle: d<lam, step(X)>/dX by torch-CPU reverse mode
-    p = oprob(w)
+    p = oprob(w, **kw)
     r = host(rec).reshape(3, 2)
     alphas = tuple((float(a[0]), float(a[1])) for a in r)
     Xo = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (w.U, w.V, w.W) if a is not None]
