@@ -114,17 +114,17 @@ def time_forward(n, precision, steps, warmup, seed=4000, basis='cell'):
         sim_time=sim_t, state_finite=bool(torch.isfinite(U).all().item()))
 
 
-def time_adjoint(precision, n=512, steps=200, every=20):
+def time_adjoint(precision, n=512, steps=200, every=20, basis='cell'):
     """Adjoint workload: 2D Euler n x n periodic smooth data (seed 5000),
     `steps` SSP-RK3 steps at the production dt of t = 0, checkpoints every
     `every` steps; J = dx dy/2 sum (U_T - U*)^2 with U* the seed-5001 field.
     Returns forward and backward (segment recompute + adjoint steps) wall
-    times of HwenoRollout."""
+    times of HwenoRollout, with the given characteristic basis."""
     import torch
     from paper_2411_11229_amd import hweno, rollout, workloads
     w = workloads.euler2d_smooth(n, seed=5000)
     tw = workloads.euler2d_smooth(n, seed=5001)
-    prob = hweno.Problem(**w.problem_kwargs(), precision=precision)
+    prob = hweno.Problem(**w.problem_kwargs(), precision=precision, basis=basis)
     s = hweno.Solver(prob)
     dt_ = prob.dtype
     mk = lambda a: torch.tensor(a, dtype=dt_, device='cuda')
@@ -367,7 +367,9 @@ def main():
     ap.add_argument('--rayleigh-taylor', action='store_true',
                     help='time the Rayleigh-Taylor example at the paper\'s meshes instead')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
-                    help='precision of the headline run')
+                    help='precision of the headline run (and of --adjoint-only)')
+    ap.add_argument('--basis', choices=['cell', 'interface'], default='cell',
+                    help='characteristic basis of --adjoint-only')
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -383,7 +385,8 @@ def main():
         print('bench.py: no HIP device visible', file=sys.stderr)
         sys.exit(1)
     if args.adjoint_only:
-        print(json.dumps({'adjoint_f64': time_adjoint(args.precision)}))
+        print(json.dumps({f'adjoint_{args.precision}_{args.basis}':
+                          time_adjoint(args.precision, basis=args.basis)}))
         return
     if args.basis_robustness:
         print(json.dumps({'basis_robustness': basis_robustness()}))

@@ -694,7 +694,9 @@ HWENO_HD void roe_eig_vjp(const Euler<DIM>& sy, const T (&UL)[DIM + 2], const T 
 // Reverse of hweno_cell_iface<D> (the interface-basis switch): the right-face
 // value in the basis of Roe's matrix of (U0, Up), the left-face value in that
 // of (Um, U0), v~ in the cell basis; each application is reversed with its
-// basis, whose cotangent goes to the states that define it.
+// basis, whose cotangent goes to the states that define it. The three
+// applications run as one rolled loop (the index is wave-uniform), so that
+// only one application's intermediates are live at a time.
 template <int D, class Sys, typename T>
 HWENO_HD void hweno_cell_iface_vjp(const Sys& sy, const Scheme& s, double h, double ih,
                                    const T (&Um)[Sys::NC], const T (&U0)[Sys::NC],
@@ -707,7 +709,19 @@ HWENO_HD void hweno_cell_iface_vjp(const Sys& sy, const Scheme& s, double h, dou
   if constexpr (!Sys::kChar) {
     hweno_cell_vjp<D>(sy, s, h, ih, Um, U0, Up, Am, Ap, guR, guL, gat, gUm, gU0, gUp, gAm, gAp);
   } else {
-    auto apply = [&](const auto& e, int which, const T (&gout)[NC], EigBar<T>& eb) {
+#pragma unroll 1
+    for (int which = 0; which < 3; ++which) {
+      // the basis: Roe's matrix of (UL, UR) for the faces, the cell's for v~
+      const bool roe = which < 2;
+      T UL[NC], UR[NC], gout[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        UL[c] = which == 0 ? U0[c] : Um[c];
+        UR[c] = which == 0 ? Up[c] : U0[c];
+        gout[c] = which == 0 ? guR[c] : (which == 1 ? guL[c] : gat[c]);
+      }
+      const auto q = sy.prim(U0);
+      const auto e = roe ? sy.roe_eig(UL, UR) : sy.eig(q);
       T wm[NC], w0[NC], wp[NC], am[NC], ap[NC], c[NC];
       sy.template project<D>(e, Um, wm);
       sy.template project<D>(e, U0, w0);
@@ -720,44 +734,45 @@ HWENO_HD void hweno_cell_iface_vjp(const Sys& sy, const Scheme& s, double h, dou
         hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, r_, l_, t_);
         c[j] = which == 0 ? r_ : (which == 1 ? l_ : t_);
       }
+      EigBar<T> eb;
       T gc[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) gc[j] = T(0);
       unproject_vjp<D>(sy, e, c, gout, eb, gc);
-      T gwm[NC], gw0[NC], gwp[NC], gam[NC], gap[NC];
+      T gwm[NC], gw0[NC], gwp[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0); gam[j] = T(0); gap[j] = T(0);
-        hweno_point_vjp<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih,
-                           which == 0 ? (double)gc[j] : 0.0, which == 1 ? (double)gc[j] : 0.0,
-                           which == 2 ? (double)gc[j] : 0.0, gwm[j], gw0[j], gwp[j], gam[j], gap[j]);
+        gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0);
+        T gam = T(0), gap = T(0);
+        const double g = (double)gc[j];
+        hweno_point_vjp<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, which == 0 ? g : 0.0,
+                           which == 1 ? g : 0.0, which == 2 ? g : 0.0, gwm[j], gw0[j], gwp[j],
+                           gam, gap);
+        am[j] = gam;   // the projected derivatives are not needed again
+        ap[j] = gap;
       }
+      // am, ap hold their cotangents now; project_vjp reads the states only
+      project_vjp<D>(sy, e, Am, am, eb, gAm);
+      project_vjp<D>(sy, e, Ap, ap, eb, gAp);
       project_vjp<D>(sy, e, Um, gwm, eb, gUm);
       project_vjp<D>(sy, e, U0, gw0, eb, gU0);
       project_vjp<D>(sy, e, Up, gwp, eb, gUp);
-      project_vjp<D>(sy, e, Am, gam, eb, gAm);
-      project_vjp<D>(sy, e, Ap, gap, eb, gAp);
-    };
-    {
-      const auto e = sy.roe_eig(U0, Up);
-      EigBar<T> eb;
-      apply(e, 0, guR, eb);
-      roe_eig_vjp(sy, U0, Up, e, eb, gU0, gUp);
-    }
-    {
-      const auto e = sy.roe_eig(Um, U0);
-      EigBar<T> eb;
-      apply(e, 1, guL, eb);
-      roe_eig_vjp(sy, Um, U0, e, eb, gUm, gU0);
-    }
-    {
-      const auto q = sy.prim(U0);
-      const auto e = sy.eig(q);
-      EigBar<T> eb;
-      apply(e, 2, gat, eb);
-      PrimBar<T> pb;
-      eig_vjp(sy, q, e, eb, pb);
-      prim_vjp(sy, U0, q, pb, gU0);
+      if (roe) {
+        T gL[NC], gR[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) { gL[k] = T(0); gR[k] = T(0); }
+        roe_eig_vjp(sy, UL, UR, e, eb, gL, gR);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          gUm[k] += which == 1 ? gL[k] : T(0);
+          gU0[k] += which == 0 ? gL[k] : gR[k];
+          gUp[k] += which == 0 ? gR[k] : T(0);
+        }
+      } else {
+        PrimBar<T> pb;
+        eig_vjp(sy, q, e, eb, pb);
+        prim_vjp(sy, U0, q, pb, gU0);
+      }
     }
   }
 }
