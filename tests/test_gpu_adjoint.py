@@ -13,7 +13,8 @@
 * Both characteristic bases: the cell basis, and the interface basis, whose
   Roe-matrix bases depend on both cells of each face (cases '-interface').
 * Full size of the adjoint workload (512^2, 200 steps, checkpoints every 20):
-  16 random directions against finite differences of GPU rollouts.
+  16 random directions against finite differences of GPU rollouts, in both
+  characteristic bases.
 """
 import numpy as np
 import pytest
@@ -218,15 +219,17 @@ def test_rollout_gradient_matches_oracle(name, mk, steps):
         assert err <= 5e-2, f'fp32 field {k}: {err:.3e}'
 
 
-def test_full_size_rollout_gradient_finite_differences():
+@pytest.mark.parametrize("basis", ['cell', 'interface'])
+def test_full_size_rollout_gradient_finite_differences(basis):
     """The adjoint workload at full size: 2D Euler 512^2 periodic smooth data,
     200 steps (dt from the production rule at t = 0, alphas per stage, both
     recorded and frozen), checkpoints every 20 steps; the gradient of J along
     16 random unit directions against Richardson finite differences of GPU
-    rollouts with the recorded dt and alphas."""
+    rollouts with the recorded dt and alphas. Both characteristic bases."""
+    print(f'basis {basis}', flush=True)
     w = WL.euler2d_smooth(512, seed=5000)
     tw = WL.euler2d_smooth(512, seed=5001)
-    s = solver(w)
+    s = solver(w, basis=basis)
     # target: the seed-5001 field advanced 200 steps
     T = state(tw)
     t = torch.zeros(1, dtype=torch.float64, device='cuda')
