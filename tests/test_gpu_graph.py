@@ -15,8 +15,8 @@ from test_gpu_parity import dev, solver
 pytestmark = pytest.mark.gpu
 
 
-def _run(w, graph, **kw):
-    s = solver(w)
+def _run(w, graph, basis='cell', **kw):
+    s = solver(w, basis=basis)
     two = w.dim == 2
     U, V = dev(w.U), dev(w.V)
     W = dev(w.W) if two else None
@@ -32,6 +32,8 @@ def _run(w, graph, **kw):
     ('double-mach-64x16-limit-40', lambda: WL.double_mach(64), dict(max_steps=40, cfl=0.1)),
     ('euler2d-quadrants-96x80-limit-50', lambda: WL.euler2d_quadrants(96, seed=4302, ny=80),
      dict(max_steps=50)),
+    ('euler2d-quadrants-96x80-interface-limit-30',
+     lambda: WL.euler2d_quadrants(96, seed=4304, ny=80), dict(max_steps=30, basis='interface')),
 ], ids=lambda x: x if isinstance(x, str) else '')
 def test_graph_run_equals_eager_run(name, mk, kw):
     print(f'case {name}', flush=True)
