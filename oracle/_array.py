@@ -1,8 +1,11 @@
 """Array-namespace shim so the oracle runs unchanged on NumPy or on torch-CPU.
 
-Test infrastructure only. NumPy gives fast float64 runs for the pins; torch
-(CPU, float64) gives reverse-mode gradients of the very same oracle source.
-Only array plumbing lives here: no arithmetic of the method.
+Test infrastructure only. NumPy gives fast float64 runs for the pins, and
+the same source in x86 extended precision (np.longdouble arrays, 64-bit
+significands) where a comparison needs a reference whose own rounding is far
+below FP64's; torch (CPU, float64) gives reverse-mode gradients of the very
+same oracle source. Only array plumbing lives here: no arithmetic of the
+method.
 """
 import numpy as np
 
@@ -37,6 +40,8 @@ class _NP:
 
     @staticmethod
     def inv(a):
+        if a.dtype == np.longdouble and np.longdouble != np.float64:
+            return _inv_gauss_jordan(a)
         return np.linalg.inv(a)
 
     @staticmethod
@@ -55,7 +60,8 @@ class _NP:
 
     @staticmethod
     def const(c, like):
-        return np.asarray(c, dtype=np.float64)
+        dt = like.dtype if getattr(like, 'dtype', None) == np.longdouble else np.float64
+        return np.asarray(c, dtype=dt)
 
 
 class _TORCH:
@@ -97,6 +103,26 @@ class _TORCH:
     @staticmethod
     def const(c, like):
         return torch.as_tensor(c, dtype=like.dtype)
+
+
+def _inv_gauss_jordan(a):
+    """Inverse of every matrix of a stack (..., n, n) by Gauss-Jordan
+    elimination with partial pivoting, in the stack's own dtype (NumPy's
+    linalg has no extended-precision routines)."""
+    n = a.shape[-1]
+    aug = np.concatenate([a, np.broadcast_to(np.eye(n, dtype=a.dtype), a.shape)], axis=-1).copy()
+    idx = np.indices(a.shape[:-2])
+    for k in range(n):
+        piv = np.argmax(np.abs(aug[..., k:, k]), axis=-1) + k
+        kk = np.full_like(piv, k)
+        row_k = aug[(*idx, kk)].copy()
+        aug[(*idx, kk)] = aug[(*idx, piv)]
+        aug[(*idx, piv)] = row_k
+        aug[..., k, :] = aug[..., k, :] / aug[..., k, k:k + 1]
+        for i in range(n):
+            if i != k:
+                aug[..., i, :] = aug[..., i, :] - aug[..., i, k:k + 1] * aug[..., k, :]
+    return aug[..., n:]
 
 
 def ns(a):

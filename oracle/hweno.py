@@ -148,20 +148,25 @@ class Euler:
         self.g = gas_gamma
         self.dim = dim
 
-    def primitives(self, U):
-        xp = _array.ns(U)
+    def state(self, U):
+        """rho, u, v, P and H = (E + P)/rho from U (EOS of (euler1d)/(euler2d))."""
         rho = U[0]
         mu = U[1] / rho
         nu = U[2] / rho if self.dim == 2 else 0.0 * rho
         E = U[-1]
         P = (self.g - 1.0) * (E - 0.5 * rho * (mu * mu + nu * nu))
-        c = xp.sqrt(self.g * P / rho)
         H = (E + P) / rho
+        return rho, mu, nu, P, H
+
+    def primitives(self, U):
+        """state() plus the sound speed c = sqrt(gamma P / rho)."""
+        rho, mu, nu, P, H = self.state(U)
+        c = _array.ns(U).sqrt(self.g * P / rho)
         return rho, mu, nu, P, c, H
 
     def flux(self, U, d):
         xp = _array.ns(U)
-        rho, mu, nu, P, c, H = self.primitives(U)
+        rho, mu, nu, P, H = self.state(U)
         E = U[-1]
         if self.dim == 1:
             return xp.stack([rho * mu, rho * mu * mu + P, mu * (E + P)])
@@ -173,7 +178,7 @@ class Euler:
         """Textbook flux Jacobian dF/dU, shape (..., nc, nc)."""
         xp = _array.ns(U)
         g = self.g
-        rho, mu, nu, P, c, H = self.primitives(U)
+        rho, mu, nu, P, H = self.state(U)
         zero = 0.0 * rho
         one = zero + 1.0
         if self.dim == 1:
@@ -246,8 +251,8 @@ def roe_state(sys, UL, UR):
     the pressure that gives the averaged sound speed
     c^2 = (gamma-1)(H - |vel|^2/2). The Jacobian depends on the velocities and
     H only, so its eigenvectors are Roe's."""
-    rl, ul, vl, _, _, hl = sys.primitives(UL)
-    rr, ur, vr, _, _, hr = sys.primitives(UR)
+    rl, ul, vl, _, hl = sys.state(UL)
+    rr, ur, vr, _, hr = sys.state(UR)
     xp = _array.ns(UL)
     wl, wr = xp.sqrt(rl), xp.sqrt(rr)
     u = (wl * ul + wr * ur) / (wl + wr)

@@ -121,10 +121,12 @@ def test_nonlinear_weights_tend_to_linear_on_smooth_data():
     assert devs[3] < 1e-3 and devs[-1] < 1e-6, devs
 
 
+@pytest.mark.slow
 def test_fifth_order_convergence_advection():
     """P6: linear advection of the seeded C1 data to T = 2 (exact = u0) with
-    the accuracy time step; every L-infinity order from N = 40 on is >= 4.5."""
-    errs, ns = [], (20, 40, 80, 160)
+    the accuracy time step, N = 20 ... 320; every L-infinity order from
+    N = 40 on is >= 4.5."""
+    errs, ns = [], (20, 40, 80, 160, 320)
     for n in ns:
         w = WL.advection1d_modes(n, seed=1000)
         prob = O.Problem(**w.problem_kwargs())
@@ -154,3 +156,22 @@ def test_mirror_left_face_matches_direct_formula():
     _, uL, _, vL, _ = O.hweno_cell(um, u0, up, vm, vp, dx, LIN_G, LIN_D, 1e-10)
     np.testing.assert_allclose(uL, direct, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(vL, P.polyval(-0.5, P.polyder(c)) / dx, rtol=1e-11, atol=1e-11)
+
+
+def test_extended_precision_oracle_runs_the_same_source():
+    """The oracle on np.longdouble arrays (the reference of the sampled
+    full-size GPU tests) computes in extended precision and agrees with the
+    FP64 oracle to FP64 rounding on smooth 2D Euler data."""
+    if np.finfo(np.longdouble).nmant <= np.finfo(np.float64).nmant:
+        pytest.skip('no extended precision on this host')
+    w = WL.euler2d_smooth(24, seed=3300, ny=20)
+    p = O.Problem(**w.problem_kwargs())
+    a = O.max_speed(p, w.U)
+    ld = lambda x: x.astype(np.longdouble)
+    r64 = O.rhs(p, w.U, w.V, w.W, a)
+    rld = O.rhs(p, ld(w.U), ld(w.V), ld(w.W), a)
+    for x, y in zip(r64, rld):
+        assert y.dtype == np.longdouble
+        scale = np.max(np.abs(y))
+        d = float(np.max(np.abs(x.astype(np.longdouble) - y)) / scale)
+        assert 0.0 < d < 1e-12, d

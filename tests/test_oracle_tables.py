@@ -53,7 +53,7 @@ def _run(w, gamma0, basis='cell'):
     return U
 
 
-@pytest.mark.parametrize("n", [40, 80, 160, 320])
+@pytest.mark.parametrize("n", [40, 80, 160, 320, pytest.param(640, marks=pytest.mark.slow)])
 def test_table1_burgers1d(n):
     w = WL.paper_burgers1d(n)
     U = _run(w, GOLD['table1_burgers1d']['gamma0'])
@@ -86,7 +86,7 @@ def test_table3_burgers2d(n):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("n", [10, 20])
+@pytest.mark.parametrize("n", [10, 20, 40])
 def test_table4_euler2d(n):
     w = WL.paper_euler2d(n)
     U = _run(w, GOLD['table4_euler2d']['gamma0'])
