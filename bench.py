@@ -5,8 +5,10 @@ Workload (the configuration the headline metric is quoted on): 2D Euler,
 2048 x 2048 cells on [0,1]^2, seeded four-quadrant Riemann data, transmissive
 boundaries, production time step (CFL 0.6) from the fused max-wave-speed
 reduction every step. A "step" is one full SSP-RK3 step: wave-speed
-reduction, time step, three fused stage kernels. Inputs are resident in HBM
-before the timed region.
+reduction and time step (fused into the stage kernels: stage 1 takes dt from
+its alphas, stage 3 reduces the next step's alphas), three fused stage
+kernels; the timed steps are one hweno_steps call. Inputs are resident in
+HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -89,13 +91,12 @@ def time_forward(n, precision, steps, warmup, seed=4000, basis='cell'):
     W = torch.tensor(w.W, dtype=dt_, device='cuda')
     t = torch.zeros(1, dtype=torch.float64, device='cuda')
     T_END = w.t_end
-    for _ in range(warmup):
-        s.step(U, V, W, t, T_END)
+    if warmup:
+        s.steps(U, V, W, t, warmup, T_END)
     ev = HipEvents(4 * steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        s.step(U, V, W, t, T_END, events=ev.group(k))
+    s.steps(U, V, W, t, steps, T_END, events=ev.ev)     # one call: K steps, fused alphas
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms = [[ev.elapsed_ms(4 * k + j, 4 * k + j + 1) for j in range(3)] for k in range(steps)]
@@ -152,9 +153,30 @@ def time_adjoint(precision, n=512, steps=200, every=20, basis='cell'):
     return dict(forward_s=fwd, backward_s=bwd, ratio=bwd / fwd, grads_finite=ok)
 
 
+def host_cpu():
+    """Model name and logical CPU count of this host (/proc/cpuinfo)."""
+    model = 'unknown'
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                model = line.split(':', 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=usable)
+
+
 def cpu_baseline(n=1024, steps=2, seed=4000):
     """The FP64 oracle (unchanged) on a bounded sample: the same four-quadrant
-    generator at n x n, `steps` SSP-RK3 steps, one thread (about 20 s)."""
+    generator at n x n, `steps` SSP-RK3 steps; NumPy on one thread (about
+    20 s), and the same oracle source on torch-CPU float64 with the host's
+    threads (at most 16, the box's share)."""
+    import numpy as np
+    import torch
     from oracle import hweno as O
     from paper_2411_11229_amd import workloads
     try:
@@ -169,9 +191,45 @@ def cpu_baseline(n=1024, steps=2, seed=4000):
     el = time.perf_counter() - t0
     if lim is not None:
         lim.unregister() if hasattr(lim, 'unregister') else None
+    host = host_cpu()
+    threads = max(1, min(16, host['usable_cpus'] or 1))
+    old = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a))
+    t0 = time.perf_counter()
+    O.run(p, T(w.U), T(w.V), T(w.W), w.t_end, max_steps=steps)
+    el_t = time.perf_counter() - t0
+    torch.set_num_threads(old)
     return dict(value=n * n * 3 * steps / el, unit='cell-stage updates/s', cores=1,
                 kind='oracle', sample=f'2D Euler four-quadrant {n}x{n}, {steps} SSP-RK3 steps, '
-                                      f'NumPy FP64, 1 thread ({el:.1f} s)')
+                                      f'NumPy FP64, 1 thread ({el:.1f} s)',
+                host_cpu=host,
+                torch_cpu=dict(value=n * n * 3 * steps / el_t, unit='cell-stage updates/s',
+                               threads=threads,
+                               sample=f'the same sample on torch-CPU float64 ({el_t:.1f} s)'))
+
+
+def copy_bandwidth(gib=1.0, reps=20):
+    """Achievable HBM bandwidth on this GPU (context for the roofline): a
+    plain device-to-device copy of `gib` GiB, bytes read + written per
+    second, timed with HIP events over `reps` copies after a warm-up."""
+    import torch
+    n = int(gib * (1 << 30) // 8)
+    a = torch.ones(n, dtype=torch.float64, device='cuda')
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 8 / (ms * 1e-3) / 1e9
+    del a, b
+    return dict(achieved=gbs, unit='GB/s', frac_of_peak=gbs / HBM_PEAK_GBS,
+                kind=f'device copy of {gib:g} GiB (read + write), mean of {reps}')
 
 
 def traffic_record():
@@ -210,8 +268,7 @@ def _run_until(s, U, V, W, t_end, max_steps):
     t = torch.zeros(1, dtype=torch.float64, device='cuda')
     k = 0
     while k < max_steps:
-        for _ in range(32):
-            s.step(U, V, W, t, t_end)
+        s.steps(U, V, W, t, 32, t_end)
         k += 32
         try:
             s.health()
@@ -336,8 +393,7 @@ def double_mach_time(nx=1600):
         s.step(U, V, W, t, w.t_end, cfl=0.1)
         n += 1
     while float(t.item()) < w.t_end and n < 100000:
-        for _ in range(64):
-            s.step(U, V, W, t, w.t_end)
+        s.steps(U, V, W, t, 64, w.t_end)
         n += 64
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -421,6 +477,7 @@ def main():
             adjoint.update(forward_s_f32=a32['forward_s'], backward_s_f32=a32['backward_s'],
                            ratio_f32=a32['ratio'])
     cpu = None if args.no_cpu else cpu_baseline()
+    copy = copy_bandwidth()
 
     traffic = traffic_record()
     roof = dict(bound='hbm', achieved=main_run['achieved_gbs'], peak=HBM_PEAK_GBS, unit='GB/s',
@@ -429,7 +486,8 @@ def main():
                 kernel=f'stage2d_kernel<Euler<2>, {"double" if args.precision == "f64" else "float"}>',
                 algorithmic_bytes_per_launch=main_run['bytes_per_launch'],
                 avg_launch_ms=main_run['avg_stage_ms'],
-                stage_launch_ms=main_run['stage_ms_mean'])
+                stage_launch_ms=main_run['stage_ms_mean'],
+                achievable_copy_gbs=copy['achieved'])
     out = {
         'metric': '2D Euler cell-updates/s per RK stage',
         'value': main_run['value'],
@@ -449,6 +507,7 @@ def main():
                    'eps': 1e-10},
         'roofline': roof,
         'cpu_baseline': cpu,
+        'hbm_copy': copy,
         'fp32': fp32,
         'adjoint_over_forward': adjoint,
         'sim_time_reached': main_run['sim_time'],

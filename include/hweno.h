@@ -22,8 +22,9 @@
  *   - The caller owns every buffer, including the workspace ws, whose size
  *     comes from hweno_workspace_bytes and which must be passed through
  *     hweno_workspace_init once before first use. The library allocates no
- *     device memory and keeps no device state; its only global state is a
- *     host-side cache of occupancy queries. Calls on different streams
+ *     device memory and keeps no device state; its only global state is
+ *     host-side: a cache of occupancy queries and the strip-height setting of
+ *     hweno_set_strip_rows. Calls on different streams
  *     with different workspaces are independent; calls sharing a workspace
  *     must be ordered on one stream.
  *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
@@ -99,7 +100,8 @@ typedef enum { HWENO_F64 = 0, HWENO_F32 = 1 } hweno_precision;
  *   interface  Jiang and Shu's form: u^-_{i+1/2}, u^+_{i+1/2} in the
  *              eigenvectors of Roe's matrix of U_i and U_{i+1}, the modified
  *              derivative in the cell basis (three interpolations per cell).
- * Ignored for the scalar laws. The adjoint supports the cell basis only. */
+ * Ignored for the scalar laws. hweno_adjoint_step differentiates either
+ * basis. */
 typedef enum { HWENO_BASIS_CELL = 0, HWENO_BASIS_INTERFACE = 1 } hweno_char_basis;
 typedef enum {
   HWENO_DT_PRODUCTION = 0,   /* dt = cfl / (ax/dx + ay/dy)                    */
@@ -204,6 +206,31 @@ hweno_status hweno_step_profiled(const hweno_problem* prob, void* u, void* v, vo
                                  int32_t dt_rule, double cfl, double dt_fixed, double t_end,
                                  double* t, double* dt_used, double* alpha_rec, void* stages,
                                  void* ws, hipStream_t stream, hipEvent_t* events);
+
+/*
+ * nsteps consecutive SSP-RK3 steps, as nsteps calls of hweno_step (same
+ * results, bit for bit) without stage states: the per-step outputs go to
+ * dt_used[k] (device double[nsteps], may be NULL) and alpha_rec + 6k (device
+ * double[nsteps][3][2], may be NULL). The stage-1 alphas of the first step
+ * come from a reduction over the initial state; those of every later step
+ * from the epilogue of the previous step's last stage, which evaluates the
+ * spectral radii of the new state as it stores it (no separate pass).
+ * Steps past t_end leave the state untouched (dt_used 0). `events`: NULL or
+ * a host array of 4 * nsteps hipEvent_t, recorded as in hweno_step_profiled
+ * for each step.
+ */
+hweno_status hweno_steps(const hweno_problem* prob, void* u, void* v, void* w, int32_t nsteps,
+                         int32_t dt_rule, double cfl, double dt_fixed, double t_end, double* t,
+                         double* dt_used, double* alpha_rec, void* ws, hipStream_t stream,
+                         hipEvent_t* events);
+
+/*
+ * Strip height (rows marched by one wavefront) of the 2D forward stage
+ * kernels, for every later launch in the process: rows > 0 forces it,
+ * 0 restores the choice of the occupancy model. Results do not depend on it
+ * (bit for bit); it exists to test exactly that. HWENO_EINVAL if rows < 0.
+ */
+hweno_status hweno_set_strip_rows(int32_t rows);
 
 /*
  * One SSP-RK3 step on (u, v, w) with a given time step (device double) and

@@ -184,6 +184,84 @@ HWENO_HD void hweno_point(T um, T u0, T up, T vm, T vp, const Scheme& s,
   vt = (T)((o0 * AT + s.d1 * ih * X) * iSd);
 }
 
+// ------------------------------------------------- HWENO-I, difference form
+// The forward stage kernels apply the same interpolation to the stencil's
+// differences, and carry every derivative multiplied by the mesh width of
+// its direction (v' = dx v, w' = dy w): then no constant of the
+// interpolation depends on the mesh. From e1 = u_i - u_{i-1},
+// e2 = u_{i+1} - u_i, S = v'_{i-1} + v'_{i+1}, D = v'_{i-1} - v'_{i+1} (a
+// linear map of the stencil, so for systems they are projected on the
+// characteristic basis in place of the five values, and u_i itself is never
+// projected) it returns the face corrections dR = u^-_{i+1/2} - u_i,
+// dL = u_i - u^+_{i-1/2} and h times the modified derivative, with the
+// arithmetic of hweno_point (there sv = S/4, dv = D/4). The smoothness
+// indicators, tau, epsilon, the weights and the combinations are evaluated
+// in double; q_l = beta_l + eps is formed directly (beta_1 = e1^2, ...).
+struct PointK {
+  double eps, gamma0, g1, d0, d1;
+  double K, hg1, A;    // 11/32 - g1/2, g1/2, 3/4 - d1
+};
+
+HWENO_HD PointK point_k(const Scheme& s) {
+  PointK k;
+  k.eps = s.eps;
+  k.gamma0 = s.gamma0;
+  k.g1 = s.g1;
+  k.d0 = s.d0;
+  k.d1 = s.d1;
+  k.K = 0.34375 - 0.5 * s.g1;
+  k.hg1 = 0.5 * s.g1;
+  k.A = 0.75 - s.d1;
+  return k;
+}
+
+template <typename T>
+HWENO_HD void hweno_point_diff(T e1_, T e2_, T S_, T D_, const PointK& k, T& dR, T& dL, T& vt) {
+  constexpr double r13 = 2.0816659994661326;    // sqrt(13/3)
+  constexpr double r781 = 6.248999919987197;    // sqrt(781/20)
+  constexpr double r1421 = 24.99636017459386;   // sqrt(1421461/2275)
+  const double e1 = (double)e1_, e2 = (double)e2_, S = (double)S_, D = (double)D_;
+  const double cdf = e1 + e2, sdf = e2 - e1;
+  // (GHYZ) closed form with the weights' square roots folded in
+  const double t1 = fma(0.6875, cdf, -0.1875 * S);
+  const double t2 = fma(r13 * 197.0 / 260.0, sdf, (r13 * 67.0 / 520.0) * D);
+  const double a3 = fma(-0.25 * r781, cdf, (0.25 * r781) * S);
+  const double a4 = fma(-0.5 * r1421, sdf, (-0.25 * r1421) * D);
+  const double q0 = fma(t1, t1, fma(t2, t2, fma(a3, a3, fma(a4, a4, k.eps))));
+  const double q1 = fma(e1, e1, k.eps), q2 = fma(e2, e2, k.eps);
+  // (nonlinear), scaled by q0 q1 q2: o_l = P + tau P / q_l
+  const double ts = fabs(q0 - q1) + fabs(q0 - q2);
+  const double tau = (0.25 * ts) * ts;
+  const double A = q1 * q2, B = q0 * q2, C = q0 * q1;
+  const double P = A * q0;
+  const double o0 = fma(A, tau, P), o1 = fma(B, tau, P), o2 = fma(C, tau, P);
+  const double o12 = o1 + o2;
+  const double Sg = fma(k.gamma0, o0, k.g1 * o12);
+  const double Sd = fma(k.d0, o0, k.d1 * o12);
+  const double inv = rcp_nr(Sg * Sd);
+  const double iSg = Sd * inv, iSd = Sg * inv;
+  // (interp) and its mirror image, (limiter)
+  const double X = fma(o1, e1, o2 * e2);
+  const double base = fma(k.K, cdf, -0.09375 * S);
+  const double m = fma(0.21875, sdf, 0.046875 * D);
+  const double P1 = fma(o0, base, k.hg1 * X), P2 = o0 * m;
+  dR = (T)((P1 + P2) * iSg);
+  dL = (T)((P1 - P2) * iSg);
+  const double AT = fma(k.A, cdf, -0.25 * S);
+  vt = (T)(fma(o0, AT, k.d1 * X) * iSd);
+}
+
+// (P'xi) and its mirror through the same differences, times h (linear, so
+// valid in conserved or characteristic variables):
+//   h v^-_{i+1/2} = -3/16 e1 + 21/16 e2 - S/16 + D/8,
+//   h v^+_{i-1/2} = 21/16 e1 - 3/16 e2 - S/16 - D/8.
+template <typename T>
+HWENO_HD void face_derivs_diff(T e1, T e2, T S, T D, T& vR, T& vL) {
+  const T s = T(-0.0625) * S;
+  vR = fma(T(-0.1875), e1, fma(T(1.3125), e2, fma(T(0.125), D, s)));
+  vL = fma(T(1.3125), e1, fma(T(-0.1875), e2, fma(T(-0.125), D, s)));
+}
+
 // (P'xi) and its mirror: v^-_{i+1/2} = p0'(x_{i+1/2}), v^+_{i-1/2} = p0'(x_{i-1/2}).
 // Linear in the data, hence the same in conserved or characteristic variables.
 template <typename T>
@@ -226,6 +304,9 @@ struct Advection {
   template <typename T> struct Prim {};
   template <typename T>
   HWENO_HD Prim<T> prim(const T (&)[NC]) const { return {}; }
+  template <typename T> struct CellEig { Prim<T> q; };
+  template <typename T>
+  HWENO_HD CellEig<T> cell_eig(const T (&)[NC]) const { return {}; }
   template <int D, typename T>
   HWENO_HD void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
     F[0] = T(D == 0 ? a : b) * U[0];
@@ -256,6 +337,9 @@ struct Burgers {
   template <typename T> struct Prim {};
   template <typename T>
   HWENO_HD Prim<T> prim(const T (&)[NC]) const { return {}; }
+  template <typename T> struct CellEig { Prim<T> q; };
+  template <typename T>
+  HWENO_HD CellEig<T> cell_eig(const T (&)[NC]) const { return {}; }
   template <int D, typename T>
   HWENO_HD void flux(const T (&U)[NC], const Prim<T>&, T (&F)[NC]) const {
     F[0] = T(0.5) * U[0] * U[0];
@@ -490,6 +574,77 @@ struct Euler {
       U[3] = e.H * a + (vn * e.c) * dd + e.k * c[1] + vt * c[2];
     }
   }
+  // The cell basis of both directions for the difference form of the HWENO
+  // (hweno_cell_diff): the primitives, c, H, and the coefficients with the
+  // halves of the closed-form L folded in (b1/2, b2/2, 1/(2c)); u c, v c for
+  // the back-projection.
+  template <typename T>
+  struct CellEig {
+    Prim<T> q;
+    T c, H, b1h, b2h, ich, muc, nuc;
+  };
+  template <typename T>
+  HWENO_HD CellEig<T> cell_eig(const T (&U)[NC]) const {
+    CellEig<T> e;
+    e.q = prim(U);
+    const T c2 = T(gas) * e.q.p * e.q.ir;
+    const T ic = rsqrt_nr(c2);
+    e.c = c2 * ic;
+    e.H = e.q.Ep * e.q.ir;
+    e.b1h = (T(0.5 * (gas - 1.0)) * ic) * ic;
+    e.b2h = e.b1h * e.q.k;
+    e.ich = T(0.5) * ic;
+    e.muc = e.q.mu * e.c;
+    e.nuc = e.q.nu * e.c;
+    return e;
+  }
+  // w = L x (the same L as project): with s' = s/2 and t' = t/2,
+  // w = (s' + t', x0 - 2 s', x2 - v x0 | x1 - u x0, s' - t').
+  template <int D, typename T>
+  HWENO_HD void project_half(const CellEig<T>& e, const T (&x)[NC], T (&w)[NC]) const {
+    if constexpr (DIM == 1) {
+      const T sh = fma(e.b2h, x[0], -e.b1h * fma(e.q.mu, x[1], -x[2]));
+      const T th = e.ich * fma(e.q.mu, x[0], -x[1]);
+      w[0] = sh + th;
+      w[1] = fma(T(-2), sh, x[0]);
+      w[2] = sh - th;
+    } else {
+      const T in = fma(e.q.mu, x[1], fma(e.q.nu, x[2], -x[3]));
+      const T sh = fma(e.b2h, x[0], -e.b1h * in);
+      const T th = D == 0 ? e.ich * fma(e.q.mu, x[0], -x[1]) : e.ich * fma(e.q.nu, x[0], -x[2]);
+      w[0] = sh + th;
+      w[1] = fma(T(-2), sh, x[0]);
+      w[2] = D == 0 ? fma(-e.q.nu, x[0], x[2]) : fma(-e.q.mu, x[0], x[1]);
+      w[3] = sh - th;
+    }
+  }
+  // out = base + R c (NEG: base - R c); base null: R c.
+  template <int D, bool NEG, typename T>
+  HWENO_HD void unproject_add(const CellEig<T>& e, const T (&c)[NC], const T* base,
+                              T (&out)[NC]) const {
+    const T sg = NEG ? T(-1) : T(1);
+    auto b = [&](int j) { return base ? base[j] : T(0); };
+    if constexpr (DIM == 1) {
+      const T a = c[0] + c[2], dd = c[2] - c[0];
+      const T s0 = a + c[1];
+      out[0] = fma(sg, s0, b(0));
+      out[1] = fma(sg * e.q.mu, s0, fma(sg * e.c, dd, b(1)));
+      out[2] = fma(sg * e.H, a, fma(sg * e.muc, dd, fma(sg * e.q.k, c[1], b(2))));
+    } else {
+      const T a = c[0] + c[3], dd = c[3] - c[0];
+      const T s0 = a + c[1];
+      out[0] = fma(sg, s0, b(0));
+      if (D == 0) {
+        out[1] = fma(sg * e.q.mu, s0, fma(sg * e.c, dd, b(1)));
+        out[2] = fma(sg * e.q.nu, s0, fma(sg, c[2], b(2)));
+        out[3] = fma(sg * e.H, a, fma(sg * e.muc, dd, fma(sg * e.q.k, c[1], fma(sg * e.q.nu, c[2], b(3)))));
+      } else {
+        out[1] = fma(sg * e.q.mu, s0, fma(sg, c[2], b(1)));
+        out[2] = fma(sg * e.q.nu, s0, fma(sg * e.c, dd, b(2)));
+        out[3] = fma(sg * e.H, a, fma(sg * e.nuc, dd, fma(sg * e.q.k, c[1], fma(sg * e.q.mu, c[2], b(3)))));
+      }
+    }
+  }
   template <int D, typename T>
   HWENO_HD double speed(const T (&U)[NC]) const {
     const double r = (double)U[0];
@@ -620,6 +775,46 @@ HWENO_HD void hweno_cell(const Sys& sy, const Scheme& s, double h, double ih,
                          const T (&Am)[Sys::NC], const T (&Ap)[Sys::NC], T (&uR)[Sys::NC],
                          T (&uL)[Sys::NC], T (&at)[Sys::NC]) {
   hweno_cell_q<D>(sy, s, h, ih, sy.prim(U0), Um, U0, Up, Am, Ap, uR, uL, at);
+}
+
+// HWENO-I on one cell in direction D, difference form (forward kernels): from
+// the conserved-variable differences E1 = U_i - U_{i-1}, E2 = U_{i+1} - U_i
+// and the sums S = A'_{i-1} + A'_{i+1}, Dd = A'_{i-1} - A'_{i+1} of the
+// derivative along D times the mesh width (A' = h A), it returns u at both
+// faces, h times the modified derivative and h times the face derivatives of
+// (P'xi). Systems project the four differences on the cell's characteristic
+// basis (remarks on the local characteristic decomposition in sections 2 and
+// 3), interpolate every characteristic variable and project the corrections
+// back onto U_i; the face derivatives are linear and taken component-wise.
+template <int D, class Sys, typename T>
+HWENO_HD void hweno_cell_diff(const Sys& sy, const PointK& k,
+                              const typename Sys::template CellEig<T>& ce,
+                              const T (&U0)[Sys::NC], const T (&E1)[Sys::NC],
+                              const T (&E2)[Sys::NC], const T (&S)[Sys::NC],
+                              const T (&Dd)[Sys::NC], T (&uR)[Sys::NC], T (&uL)[Sys::NC],
+                              T (&at)[Sys::NC], T (&vR)[Sys::NC], T (&vL)[Sys::NC]) {
+  constexpr int NC = Sys::NC;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) face_derivs_diff(E1[c], E2[c], S[c], Dd[c], vR[c], vL[c]);
+  if constexpr (!Sys::kChar) {
+    T dR, dL;
+    hweno_point_diff<T>(E1[0], E2[0], S[0], Dd[0], k, dR, dL, at[0]);
+    uR[0] = U0[0] + dR;
+    uL[0] = U0[0] - dL;
+  } else {
+    T e1[NC], e2[NC], sc[NC], dc[NC];
+    sy.template project_half<D>(ce, E1, e1);
+    sy.template project_half<D>(ce, E2, e2);
+    sy.template project_half<D>(ce, S, sc);
+    sy.template project_half<D>(ce, Dd, dc);
+    T cr[NC], cl[NC], ct[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      hweno_point_diff<T>(e1[j], e2[j], sc[j], dc[j], k, cr[j], cl[j], ct[j]);
+    sy.template unproject_add<D, false>(ce, cr, U0, uR);
+    sy.template unproject_add<D, true>(ce, cl, U0, uL);
+    sy.template unproject_add<D, false>(ce, ct, (const T*)nullptr, at);
+  }
 }
 
 // ------------------------------------------------------------- index maps

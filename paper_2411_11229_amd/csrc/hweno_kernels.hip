@@ -35,6 +35,32 @@ struct SplitRule {
   double state[2][4];
 };
 
+// Workspace scalars of a time step. The alpha accumulators hold the
+// non-negative doubles' bit patterns (atomic max): acc[0..1] the stage-2
+// alphas (written by stage 1), acc[2..3] the stage-3 alphas (by stage 2),
+// acc[4..5] the next stage-1 alphas, i.e. those of the step's result (by
+// stage 3, or by the seeding pass before a run's first step).
+struct StepScalars {
+  unsigned long long acc[6];
+  double dt;
+  double t0;                      // the step's start time
+  double tnew;                    // its end time (t0 + dt, or t_end when clipped)
+  int active;
+  unsigned flags;
+};
+
+// Time-step control of a stage-1 launch that computes dt itself (a2): from
+// its alphas by `rule` (production cfl / (ax/hx + ay/hy) with hx, hy = dx, dy;
+// accuracy the same with dx^(5/3), dy^(5/3); fixed dt_fixed), clipped so that
+// t + dt does not pass t_end. sc null: dt is given (frozen steps, adjoint).
+struct StepCtl {
+  StepScalars* sc;
+  double* t;                      // the caller's time (read by stage 1, advanced by stage 2)
+  double* dt_used;                // or null
+  int rule, dim;
+  double cfl, dt_fixed, t_end, hx, hy;
+};
+
 template <typename T>
 struct StageArgs {
   const T* U;  const T* V;  const T* W;   // stage state X (W null in 1D)
@@ -42,8 +68,8 @@ struct StageArgs {
   T* Uo; T* Vo; T* Wo;                    // new state (stages) or L^1..L^3 (rhs)
   T* Vt; T* Wt;                           // stage 1: V~^n, W~^n; rhs: modified derivatives
   const double* alpha;                    // [2] LF alphas of this stage
-  const double* dt;                       // stages: time step
-  const int* active;                      // stages: 0 = the step is skipped
+  const double* dt;                       // stages 2-3, frozen steps: time step
+  const int* active;                      // stages 2-3: 0 = the step is skipped
   unsigned long long* alpha_next;         // [2] atomic max of the new state's speeds, or null
   unsigned* flags;                        // sticky state flags, or null
   double* alpha_rec;                      // [2] record of the alphas used, or null
@@ -56,8 +82,72 @@ struct StageArgs {
   SplitRule sp[2];                        // split y sides (low, high)
   const double* t0;                       // step start time (device), null: t = 0
   double tc;                              // this stage's time: t0 + tc dt
+  StepCtl ctl;                            // stage 1 computing dt, stages 2-3 of such a step
   Scheme s;
+  PointK pk;                              // HWENO point constants (difference form)
 };
+
+// Start of a stage launch: the stage's dt and time, and whether the step is
+// active. A stage 1 with time-step control computes dt itself from its alphas
+// (every block alike); its first lane also publishes dt, the step's times and
+// the record of the alphas, and clears the stage-3 accumulators. Stage 2 of
+// such a step advances the caller's time and clears the next-step
+// accumulators (read by stage 1, written again by stage 3); stage 3 clears
+// the stage-2 accumulators. Each clear comes after the last read of those
+// accumulators and before their next writer, one kernel boundary apart.
+template <int MODE, typename T>
+__device__ __forceinline__ bool stage_begin(const StageArgs<T>& A, bool leader, double& dt,
+                                            double& tstage) {
+  dt = 0.0;
+  tstage = 0.0;
+  if (MODE == kRhs) return true;
+  const StepCtl& c = A.ctl;
+  if (MODE == kStage1 && c.sc) {
+    const double ax = A.alpha[0], ay = c.dim == 2 ? A.alpha[1] : 0.0;
+    double d = c.rule == HWENO_DT_FIXED ? c.dt_fixed
+                                        : c.cfl / (c.dim == 2 ? ax / c.hx + ay / c.hy : ax / c.hx);
+    const double t0 = *c.t;
+    const bool active = t0 < c.t_end;
+    double tn = t0 + d;
+    if (!active) {
+      d = 0.0;
+      tn = t0;
+    } else if (tn >= c.t_end) {
+      d = c.t_end - t0;
+      tn = c.t_end;
+    }
+    if (leader) {
+      c.sc->dt = d;
+      c.sc->t0 = t0;
+      c.sc->tnew = tn;
+      c.sc->active = active ? 1 : 0;
+      c.sc->acc[2] = c.sc->acc[3] = 0ull;
+      if (c.dt_used) *c.dt_used = d;
+      if (A.alpha_rec) {
+        A.alpha_rec[0] = ax;
+        A.alpha_rec[1] = ay;
+      }
+    }
+    dt = d;
+    tstage = t0;
+    return active;
+  }
+  if (A.active && *A.active == 0) return false;
+  dt = *A.dt;
+  tstage = A.t0 ? *A.t0 + A.tc * dt : 0.0;
+  if (leader) {
+    if (A.alpha_rec) {
+      A.alpha_rec[0] = A.alpha[0];
+      A.alpha_rec[1] = A.ctl.dim == 1 ? 0.0 : A.alpha[1];
+    }
+    if (c.sc && MODE == kStage2) {
+      *c.t = c.sc->tnew;
+      c.sc->acc[4] = c.sc->acc[5] = 0ull;
+    }
+    if (c.sc && MODE == kStage3) c.sc->acc[0] = c.sc->acc[1] = 0ull;
+  }
+  return true;
+}
 
 // ---------------------------------------------------------------- helpers
 // Element idx of a state array through a 32-bit byte offset from the uniform
@@ -113,42 +203,70 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) 
 }
 
 // ------------------------------------------------------ x-direction sweep
+// (Cd-1)-(DfDh) at one interface, with the derivative fluxes carried times
+// the mesh width h (h' = h f'(u) v): D(f) and h D(h).
+template <typename T>
+__device__ __forceinline__ void central_corr_k(T fm1, T f0, T fp1, T fp2, T hm1, T hp2, T& Df,
+                                               T& Dh) {
+  const T s4 = (fm1 + fp2) - (f0 + fp1);
+  Df = fma(T(-97.0 / 1920.0), s4, T(-19.0 / 960.0) * (hm1 - hp2));
+  Dh = fma(T(697.0 / 5184.0), fm1 - fp2, fma(T(-61.0 / 192.0), f0 - fp1, T(37.0 / 864.0) * (hm1 + hp2)));
+}
+
 // Steps 1-4 of section 2 along x for the row held by the wavefront (one cell
-// per lane). Inputs: this lane's U, V (= u_x) and, with NF == 3, W (= u_y).
-// Outputs: residual parts -(F_{i+1/2} - F_{i-1/2})/dx of the u-, v- and
-// w-equations (the last from the mixed flux eta = f'(u) w), accumulated in
-// double, and the modified derivative v~. Valid on lanes 2..61.
+// per lane). Inputs: this lane's U, V' = dx u_x and, with NF == 3,
+// W' = dy u_y (derivatives carried times their mesh width, see
+// hweno_cell_diff), and the cell's characteristic basis and primitives
+// `ce`. Outputs: the residual parts -(F_{i+1/2} - F_{i-1/2})/dx of the u-,
+// v- and w-equations (the last from the mixed flux eta = f'(u) w),
+// accumulated in double and unscaled, and dx v~. Valid on lanes 2..61.
 template <int NF, bool IFACE, class Sys, typename T>
-__device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, double alpha,
+__device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, const PointK& pk,
+                                        double alpha,
+                                        const typename Sys::template CellEig<T>& ce,
                                         const T (&U)[Sys::NC], const T (&V)[Sys::NC],
                                         const T (&W)[Sys::NC], double (&RU)[Sys::NC],
                                         double (&RV)[Sys::NC], double (&RW)[Sys::NC],
                                         T (&vt)[Sys::NC]) {
   constexpr int NC = Sys::NC;
-  const T h = T(s.dx), ih = T(s.idx);
-  T Um[NC], Up[NC], Vm[NC], Vp[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    Um[c] = from_prev(U[c]);
-    Up[c] = from_next(U[c]);
-    Vm[c] = from_prev(V[c]);
-    Vp[c] = from_next(V[c]);
-  }
-  // Step 1: HWENO once per cell -> u at both faces, v~ at the centre
+  // Step 1: HWENO once per cell -> u at both faces, v~ at the centre, and the
+  // face derivatives of (P'xi)
   T uR[NC], uL[NC], vR[NC], vL[NC];
-  const auto q = sy.prim(U);
-  hweno_cell_b<0, IFACE>(sy, s, s.dx, s.idx, q, Um, U, Up, Vm, Vp, uR, uL, vt);
+  if constexpr (IFACE) {
+    T Um[NC], Up[NC], Vm[NC], Vp[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Vm[c], Vp[c], ih, vR[c], vL[c]);
-  // pointwise f, h = f'(u) v, eta = f'(u) w at the cell centre
-  T f[NC], hf[NC], e[NC];
-  {
-    sy.template flux<0>(U, q, f);
-    sy.template jac<0>(U, q, V, hf);
-    if constexpr (NF == 3) sy.template jac<0>(U, q, W, e);
+    for (int c = 0; c < NC; ++c) {
+      Um[c] = from_prev(U[c]);
+      Up[c] = from_next(U[c]);
+      Vm[c] = from_prev(V[c]);
+      Vp[c] = from_next(V[c]);
+    }
+    // mesh width 1 for the scaled derivatives
+    hweno_cell_b<0, true>(sy, s, 1.0, 1.0, ce.q, Um, U, Up, Vm, Vp, uR, uL, vt);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) face_derivs(Um[c], U[c], Up[c], Vm[c], Vp[c], T(1), vR[c], vL[c]);
+  } else {
+    // the stencil as differences: E1 = U_i - U_{i-1}, E2 = U_{i+1} - U_i
+    // (E1 of the next lane), S and D the sum and difference of V'_{i-1}, V'_{i+1}
+    T E1[NC], E2[NC], Sv[NC], Dv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) E1[c] = U[c] - from_prev(U[c]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      E2[c] = from_next(E1[c]);
+      const T vm = from_prev(V[c]), vp = from_next(V[c]);
+      Sv[c] = vm + vp;
+      Dv[c] = vm - vp;
+    }
+    hweno_cell_diff<0>(sy, pk, ce, U, E1, E2, Sv, Dv, uR, uL, vt, vR, vL);
   }
-  // Lax-Friedrichs halves of this cell's faces (flux-LF): the minus side of
-  // x_{i+1/2} and the plus side of x_{i-1/2}
+  // pointwise f, h' = f'(u) v', eta' = f'(u) w' at the cell centre
+  T f[NC], hf[NC], e[NC];
+  sy.template flux<0>(U, ce.q, f);
+  sy.template jac<0>(U, ce.q, V, hf);
+  if constexpr (NF == 3) sy.template jac<0>(U, ce.q, W, e);
+  // Lax-Friedrichs sums of this cell's faces (flux-LF), halved at the
+  // interface: f(u^-) + a u^- at x_{i+1/2}, f(u^+) - a u^+ at x_{i-1/2}
   T mF[NC], mH[NC], pF[NC], pH[NC];
   {
     const T a = T(alpha);
@@ -161,56 +279,68 @@ __device__ __forceinline__ void sweep_x(const Sys& sy, const Scheme& s, double a
     sy.template jac<0>(uL, ql, vL, hl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      mF[c] = T(0.5) * (fr[c] + a * uR[c]);
-      mH[c] = T(0.5) * (hr[c] + a * vR[c]);
-      pF[c] = T(0.5) * (fl[c] - a * uL[c]);
-      pH[c] = T(0.5) * (hl[c] - a * vL[c]);
+      mF[c] = fma(a, uR[c], fr[c]);
+      mH[c] = fma(a, vR[c], hr[c]);
+      pF[c] = fma(-a, uL[c], fl[c]);
+      pH[c] = fma(-a, vL[c], hl[c]);
     }
   }
-  // Steps 2-3 at x_{i+1/2}, then Step 4
+  // Steps 2-3 at x_{i+1/2}, then Step 4; the v-equation's fluxes carry a
+  // factor dx, eta' a factor dy, removed in the flux differences
+  const double cv = s.idx * s.idx, cw = s.idx * s.idy * (1.0 / 12.0);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const T fm1 = from_prev(f[c]), fp1 = from_next(f[c]), fp2 = from_next2(f[c]);
-    const T hm1 = from_prev(hf[c]), hp2 = from_next2(hf[c]);
+    const T fm1 = from_prev(f[c]), fp1 = from_next(f[c]), fp2 = from_next(fp1);
+    const T hm1 = from_prev(hf[c]), hp1 = from_next(hf[c]), hp2 = from_next(hp1);
     T Df, Dh;
-    central_corr(fm1, f[c], fp1, fp2, hm1, hp2, h, ih, Df, Dh);
-    const T Fi = mF[c] + from_next(pF[c]) + Df;
-    const T Hi = mH[c] + from_next(pH[c]) + Dh;
-    RU[c] = -((double)Fi - (double)from_prev(Fi)) * s.idx;
-    RV[c] = -((double)Hi - (double)from_prev(Hi)) * s.idx;
+    central_corr_k(fm1, f[c], fp1, fp2, hm1, hp2, Df, Dh);
+    const T Fi = fma(T(0.5), mF[c] + from_next(pF[c]), Df);
+    const T Hi = fma(T(0.5), mH[c] + from_next(pH[c]), Dh);
+    RU[c] = ((double)from_prev(Fi) - (double)Fi) * s.idx;
+    RV[c] = ((double)from_prev(Hi) - (double)Hi) * cv;
     if constexpr (NF == 3) {
-      const T Ei = mixed_face(from_prev(e[c]), e[c], from_next(e[c]), from_next2(e[c]));
-      RW[c] = -((double)Ei - (double)from_prev(Ei)) * s.idx;
+      // (mixed) times 12: 7 (e_i + e_{i+1}) - (e_{i-1} + e_{i+2})
+      const T em1 = from_prev(e[c]), ep1 = from_next(e[c]), ep2 = from_next(ep1);
+      const T Ei = fma(T(7), e[c] + ep1, -(em1 + ep2));
+      RW[c] = ((double)from_prev(Ei) - (double)Ei) * cw;
     }
   }
 }
 
-// RK combination of one output cell (all in double, one rounding at store).
-// The stage-3 weight 1/3 multiplies (within an ulp of dividing by 3, and an
+// The Runge-Kutta combination (fully-hweno)/(2Dfully-hweno) of one value,
+// written as a part known before the y-sweep's flux difference L_y and the
+// weight of L_y: X_new = rk_part + rk_wl dt L_y, with
+//   stage 1: X + dt L_x,  stage 2: 3/4 B + 1/4 (X + dt L_x),
+//   stage 3: 1/3 B + 2/3 (X + dt L_x),  operator only (rhs): L_x.
+// All in double, one rounding at the store. The stage-3 weights multiply (an
 // FP64 division would cost about ten instructions per value).
 template <int MODE>
-__device__ __forceinline__ double rk(double x, double base, double dt, double L) {
-  if constexpr (MODE == kStage1) return x + dt * L;
-  else if constexpr (MODE == kStage2) return 0.75 * base + 0.25 * (x + dt * L);
-  else if constexpr (MODE == kStage3) return (1.0 / 3.0) * base + (2.0 / 3.0) * (x + dt * L);
-  else return L;
+__device__ __forceinline__ double rk_part(double x, double base, double dt, double Lx) {
+  if constexpr (MODE == kStage1) return fma(dt, Lx, x);
+  else if constexpr (MODE == kStage2) return fma(0.25 * dt, Lx, fma(0.25, x, 0.75 * base));
+  else if constexpr (MODE == kStage3)
+    return fma((2.0 / 3.0) * dt, Lx, fma(2.0 / 3.0, x, (1.0 / 3.0) * base));
+  else return Lx;
+}
+template <int MODE>
+__device__ __forceinline__ double rk_wl(double dt) {
+  if constexpr (MODE == kStage1) return dt;
+  else if constexpr (MODE == kStage2) return 0.25 * dt;
+  else if constexpr (MODE == kStage3) return (2.0 / 3.0) * dt;
+  else return 1.0;
 }
 
 // ------------------------------------------------------------ 1D stage kernel
 template <class Sys, typename T, int MODE, bool IFACE>
 __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
-  if (MODE != kRhs && A.active && *A.active == 0) return;
   const int lane = threadIdx.x;
+  double dt, tstage;
+  if (!stage_begin<MODE>(A, blockIdx.x == 0 && lane == 0, dt, tstage)) return;
   const int col = blockIdx.x * kXOut - kHalo + lane;
   const int g = map_index(col, A.nx, A.bc[0], A.bc[1]);
   const bool out = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
   const double ax = A.alpha[0];
-  const double dt = MODE == kRhs ? 0.0 : *A.dt;
-  if (MODE != kRhs && A.alpha_rec && blockIdx.x == 0 && lane == 0) {
-    A.alpha_rec[0] = ax;
-    A.alpha_rec[1] = 0.0;
-  }
   T U[NC], V[NC], W[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -230,9 +360,13 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
       }
     }
   }
+  // derivatives carried times dx (see sweep_x)
+#pragma unroll
+  for (int c = 0; c < NC; ++c) V[c] = T(A.s.dx) * V[c];
   double RU[NC], RV[NC], RW[NC];
   T vt[NC];
-  sweep_x<2, IFACE>(sy, A.s, ax, U, V, W, RU, RV, RW, vt);
+  const auto ce = sy.cell_eig(U);
+  sweep_x<2, IFACE>(sy, A.s, A.pk, ax, ce, U, V, W, RU, RV, RW, vt);
   double smax = 0.0;
   unsigned flag = 0;
   if (out) {
@@ -242,10 +376,11 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
       const int o = c * A.plane + col;
       const double ub = MODE >= kStage2 ? (double)A.Ub[o] : 0.0;
       const double vb = MODE >= kStage2 ? (double)A.Vb[o] : 0.0;
-      Un[c] = (T)rk<MODE>((double)U[c], ub, dt, RU[c]);
+      const double vtc = (double)vt[c] * A.s.idx;
+      Un[c] = (T)rk_part<MODE>((double)U[c], ub, dt, RU[c]);
       A.Uo[o] = Un[c];
-      A.Vo[o] = (T)rk<MODE>((double)vt[c], vb, dt, RV[c]);
-      if (MODE == kStage1 || MODE == kRhs) A.Vt[o] = vt[c];
+      A.Vo[o] = (T)rk_part<MODE>(vtc, vb, dt, RV[c]);
+      if (MODE == kStage1 || MODE == kRhs) A.Vt[o] = (T)vtc;
     }
     if (A.alpha_next) {
       double sy_;
@@ -271,19 +406,18 @@ __global__ __launch_bounds__(64) void stage1d_kernel(StageArgs<T> A, Sys sy) {
 // use the kernel without this code, whose register allocation it would
 // disturb.
 template <class Sys, bool WALLS, typename T>
-__device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int col, int gcol,
-                                         bool xwall, bool xm, int xf, T (&U)[Sys::NC],
-                                         T (&V)[Sys::NC], T (&W)[Sys::NC]) {
+__device__ __forceinline__ void load_row(const StageArgs<T>& A, double tstage, int r, int col,
+                                         int gcol, T (&U)[Sys::NC], T (&V)[Sys::NC],
+                                         T (&W)[Sys::NC], int& split_rule) {
   int gr = map_index(r, A.ny, A.bc[2], A.bc[3]);
   // split side: this lane's rule from its x, the ghost row's y and the
   // stage time (0: transmissive, 1: reflective, 2 + k: fixed state k)
-  int split_rule = -1;
+  split_rule = -1;
   if constexpr (WALLS) {
     const int yside = r < 0 ? 0 : (r >= A.ny ? 1 : -1);
     if (yside >= 0 && A.bc[2 + yside] == kBcSplit) {
       const SplitRule& sr = A.sp[yside];
-      const double t = A.t0 ? *A.t0 + A.tc * *A.dt : 0.0;
-      const double xs = sr.x0 + sr.slope * ((r + 0.5) * A.s.dy) + sr.speed * t;
+      const double xs = sr.x0 + sr.slope * ((r + 0.5) * A.s.dy) + sr.speed * tstage;
       const int k = (col + 0.5) * A.s.dx < xs ? 0 : 1;
       const int kind = sr.kind[k];
       split_rule = kind == kBcReflective ? 1 : (kind == kBcDirichlet ? 2 + k : 0);
@@ -298,6 +432,15 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int col, 
     V[c] = ld32(A.V, i);
     W[c] = ld32(A.W, i);
   }
+}
+
+// What load_row leaves to the row's first use (so that the loads stay in
+// flight until then): the ghost rules of walls, fixed states and split sides,
+// and the derivatives times their mesh width (see sweep_x).
+template <class Sys, bool WALLS, typename T>
+__device__ __forceinline__ void finish_row(const StageArgs<T>& A, int r, bool xwall, bool xm,
+                                           int xf, int split_rule, T (&U)[Sys::NC],
+                                           T (&V)[Sys::NC], T (&W)[Sys::NC]) {
   if constexpr (WALLS) {
     auto fix = [&](int side) {
 #pragma unroll
@@ -330,6 +473,11 @@ __device__ __forceinline__ void load_row(const StageArgs<T>& A, int r, int col, 
       }
     }
   }
+#pragma unroll
+  for (int c = 0; c < Sys::NC; ++c) {
+    V[c] = T(A.s.dx) * V[c];
+    W[c] = T(A.s.dy) * W[c];
+  }
 }
 
 // VAR: kVarWalls (some boundary is reflective or fixed), kVarIface (interface
@@ -343,9 +491,10 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   constexpr bool IFACE = (VAR & kVarIface) != 0;
   constexpr bool SOURCE = (VAR & kVarSource) != 0 && Sys::kChar && Sys::NC == 4;
   constexpr int NC = Sys::NC;
-  if (MODE != kRhs && A.active && *A.active == 0) return;
   const Scheme& s = A.s;
   const int lane = threadIdx.x;
+  double dt, tstage;
+  if (!stage_begin<MODE>(A, blockIdx.x == 0 && blockIdx.y == 0 && lane == 0, dt, tstage)) return;
   const int col = blockIdx.x * kXOut - kHalo + lane;
   const int gcol = map_index(col, A.nx, A.bc[0], A.bc[1]);
   const bool out_col = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
@@ -357,43 +506,64 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   const int y0 = blockIdx.y * A.rows;
   const int y1 = min(y0 + A.rows, A.ny);
   const double ax = A.alpha[0], ay = A.alpha[1];
-  const double dt = MODE == kRhs ? 0.0 : *A.dt;
-  if (MODE != kRhs && A.alpha_rec && blockIdx.x == 0 && blockIdx.y == 0 && lane == 0) {
-    A.alpha_rec[0] = ax;
-    A.alpha_rec[1] = ay;
-  }
-  const T hy = T(s.dy), ihy = T(s.idy), a_y = T(ay);
+  const T a_y = T(ay);
+  // weights of the y flux differences (fprev - F) in the new state: the
+  // stage's weight of dt L times 1/dy (and 1/(12 dy) for the mixed flux,
+  // which is carried times 12)
+  const double wl = rk_wl<MODE>(dt) * s.idy;
+  // the v-equation's y-fluxes carry 12 dx, the w-equation's dy
+  const double wlv = wl * s.idx * (1.0 / 12.0), wlw = wl * s.idy;
 
-  // register ring over rows (a = r-2, b = r-1 at the top of iteration r)
-  T Ua[NC], Ub[NC], Va[NC], Vb[NC], Wa[NC], Wb[NC];
-  // the pointwise y-fluxes g, theta, xi of rows r-3, r-2, r-1 live in LDS,
-  // slot (row mod 3); each lane only touches its own column
+  // Rows march upwards; at iteration r the rows r-2, r-1 (registers) and r
+  // (just loaded) are present. Iteration r does: the pointwise y-fluxes of
+  // row r; the HWENO of row r-1 in y, then in x with the same
+  // characteristic basis; the y-interface (r-2)+1/2 and with it the output
+  // row r-2; the x-sweep of row r-1, whose flux difference and RK
+  // combination wait in LDS (pend) until the next iteration adds the
+  // y-part. U, W of rows r-2, r-1 and V of row r-1 stay in registers.
+  T Ua[NC], Ub[NC], Wa[NC], Wb[NC], Vb[NC];
+  // pointwise g, theta, xi of rows r-3, r-2, r-1, slot (row mod 3); each
+  // lane only touches its own column
   __shared__ T ring[3][3][NC][kWave];
-  int slot = ((y0 - 2) % 3 + 3) % 3;   // slot of row r (and of row r-3)
-  // top-face LF halves (g, theta) and w~ of rows r-2 and r-1, by row parity
-  __shared__ T topr[2][3][NC][kWave];
-  // y-interface fluxes g, theta, xi at (r-3)+1/2, in LDS (own column only):
-  // registers are the marcher's scarce resource
+  int slot = ((y0 - 2) % 3 + 3) % 3;     // slot of row r (and of row r-3)
+  // Lax-Friedrichs sums g(u) + a u, theta + a w at the top face of row r-2
+  __shared__ T topr[2][NC][kWave];
+  // y-interface fluxes g, theta, 12 xi at (r-3)+1/2
   __shared__ T fprev[3][NC][kWave];
+  // RK combination of row r-2 (u, v, w) without its y flux difference
+  __shared__ double pend[3][NC][kWave];
   double smx = 0.0, smy = 0.0;
   unsigned flag = 0;
 
   T Un[NC], Vn[NC], Wn[NC];
-  load_row<Sys, WALLS>(A, y0 - 2, col, gcol, xwall, xm, xf, Un, Vn, Wn);
+  T Bu[NC], Bv[NC], Bw[NC];              // RK base of row r-1 (stages 2-3)
+  // The y-work below runs in every iteration, also in the first ones, whose
+  // results are never used (so that it forms one block of straight-line code
+  // the compiler can schedule across): start from an admissible state.
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    Ua[c] = Ub[c] = T(c == 0 ? 1.0 : (c == NC - 1 ? 2.0 : 0.0));
+    Wa[c] = Wb[c] = Vb[c] = T(0);
+  }
+  int rule_n;
+  load_row<Sys, WALLS>(A, tstage, y0 - 2, col, gcol, Un, Vn, Wn, rule_n);
   for (int r = y0 - 2; r < y1 + 2; ++r) {
     T Uc[NC], Vc[NC], Wc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) { Uc[c] = Un[c]; Vc[c] = Vn[c]; Wc[c] = Wn[c]; }
-    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, r + 1, col, gcol, xwall, xm, xf, Un, Vn, Wn);  // prefetch
-    // RK base of this iteration's output row, loaded early to hide latency
-    T Bu[NC], Bv[NC], Bw[NC];
-    if (MODE >= kStage2 && r >= y0 + 2 && out_col) {
+    finish_row<Sys, WALLS>(A, r, xwall, xm, xf, rule_n, Uc, Vc, Wc);
+    if (r + 1 < y1 + 2) load_row<Sys, WALLS>(A, tstage, r + 1, col, gcol, Un, Vn, Wn, rule_n);  // prefetch
+    // RK base of row r, for the x-sweep of the next iteration (rows and
+    // columns clamped into the array: the values outside are never used)
+    T Bun[NC], Bvn[NC], Bwn[NC];
+    if constexpr (MODE >= kStage2) {
+      const int rr = min(max(r, 0), A.ny - 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const unsigned idx = (unsigned)(c * A.plane + (r - 2) * A.nx + col);
-        Bu[c] = ld32(A.Ub, idx);
-        Bv[c] = ld32(A.Vb, idx);
-        Bw[c] = ld32(A.Wb, idx);
+        const unsigned idx = (unsigned)(c * A.plane + rr * A.nx + gcol);
+        Bun[c] = ld32(A.Ub, idx);
+        Bvn[c] = ld32(A.Vb, idx);
+        Bwn[c] = ld32(A.Wb, idx);
       }
     }
     // pointwise g, theta = g'(u) w, xi = g'(u) v of row r
@@ -404,13 +574,29 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
       sy.template jac<1>(Uc, q, Wc, tc);
       sy.template jac<1>(Uc, q, Vc, xc);
     }
-    // HWENO in y of row r-1 (rows r-2, r-1, r are present)
-    T mG[NC], mT[NC], pG[NC], pT[NC], wtn[NC];
-    if (r >= y0) {
+    // HWENO in y of row r-1: u at its top and bottom faces, w~, and the LF
+    // sums there
+    typename Sys::template CellEig<T> ce;
+    T mG[NC], mT[NC], pG[NC], pT[NC], wt[NC];
+    {
+      ce = sy.cell_eig(Ub);
       T uT[NC], uB[NC], wT[NC], wB[NC];
-      hweno_cell_b<1, IFACE>(sy, s, s.dy, s.idy, sy.prim(Ub), Ua, Ub, Uc, Wa, Wc, uT, uB, wtn);
+      if constexpr (IFACE) {
+        // mesh width 1 for the scaled derivatives
+        hweno_cell_b<1, true>(sy, s, 1.0, 1.0, ce.q, Ua, Ub, Uc, Wa, Wc, uT, uB, wt);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) face_derivs(Ua[c], Ub[c], Uc[c], Wa[c], Wc[c], ihy, wT[c], wB[c]);
+        for (int c = 0; c < NC; ++c) face_derivs(Ua[c], Ub[c], Uc[c], Wa[c], Wc[c], T(1), wT[c], wB[c]);
+      } else {
+        T E1[NC], E2[NC], Sw[NC], Dw[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          E1[c] = Ub[c] - Ua[c];
+          E2[c] = Uc[c] - Ub[c];
+          Sw[c] = Wa[c] + Wc[c];
+          Dw[c] = Wa[c] - Wc[c];
+        }
+        hweno_cell_diff<1>(sy, A.pk, ce, Ub, E1, E2, Sw, Dw, uT, uB, wt, wT, wB);
+      }
       T gt[NC], tt[NC], gb[NC], tb[NC];
       const auto qt = sy.prim(uT);
       sy.template flux<1>(uT, qt, gt);
@@ -420,104 +606,112 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
       sy.template jac<1>(uB, qb, wB, tb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        mG[c] = T(0.5) * (gt[c] + a_y * uT[c]);
-        mT[c] = T(0.5) * (tt[c] + a_y * wT[c]);
-        pG[c] = T(0.5) * (gb[c] - a_y * uB[c]);
-        pT[c] = T(0.5) * (tb[c] - a_y * wB[c]);
-        const int pr = (r - 1) & 1;   // row r-1
-        topr[pr][0][c][lane] = mG[c];
-        topr[pr][1][c][lane] = mT[c];
-        topr[pr][2][c][lane] = wtn[c];
+        mG[c] = fma(a_y, uT[c], gt[c]);
+        mT[c] = fma(a_y, wT[c], tt[c]);
+        pG[c] = fma(-a_y, uB[c], gb[c]);
+        pT[c] = fma(-a_y, wB[c], tb[c]);
       }
     }
-    if (r >= y0 + 1) {
-      // y-interface (r-2)+1/2: minus side = top face of row r-2, plus side =
-      // bottom face of row r-1; central correction from rows r-3..r
-      T Gn[NC], Tn[NC], Xn[NC];
+    // y-interface (r-2)+1/2: minus side = top face of row r-2, plus side =
+    // bottom face of row r-1; central correction from rows r-3..r
+    T Gn[NC], Tn[NC], Xn[NC];
+    {
+      const int s3 = slot, s2 = slot == 2 ? 0 : slot + 1, s1 = slot == 0 ? 2 : slot - 1;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        T Dg, Dt;
-        const int s3 = slot, s2 = slot == 2 ? 0 : slot + 1, s1 = slot == 0 ? 2 : slot - 1;
         const T g3 = ring[s3][0][c][lane], g2 = ring[s2][0][c][lane], g1 = ring[s1][0][c][lane];
         const T t3 = ring[s3][1][c][lane];
         const T x3 = ring[s3][2][c][lane], x2 = ring[s2][2][c][lane], x1 = ring[s1][2][c][lane];
-        central_corr(g3, g2, g1, gc[c], t3, tc[c], hy, ihy, Dg, Dt);
-        const int pa = (r - 2) & 1;   // row r-2
-        Gn[c] = topr[pa][0][c][lane] + pG[c] + Dg;
-        Tn[c] = topr[pa][1][c][lane] + pT[c] + Dt;
-        Xn[c] = mixed_face(x3, x2, x1, xc[c]);
+        T Dg, Dt;
+        central_corr_k(g3, g2, g1, gc[c], t3, tc[c], Dg, Dt);
+        Gn[c] = fma(T(0.5), topr[0][c][lane] + pG[c], Dg);
+        Tn[c] = fma(T(0.5), topr[1][c][lane] + pT[c], Dt);
+        Xn[c] = fma(T(7), x2 + x1, -(x3 + xc[c]));
       }
+    }
+    // row r takes the ring slot of row r-3; row r-1's top-face sums replace
+    // row r-2's
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {   // row r takes the slot of row r-3
-        ring[slot][0][c][lane] = gc[c];
-        ring[slot][1][c][lane] = tc[c];
-        ring[slot][2][c][lane] = xc[c];
+    for (int c = 0; c < NC; ++c) {
+      ring[slot][0][c][lane] = gc[c];
+      ring[slot][1][c][lane] = tc[c];
+      ring[slot][2][c][lane] = xc[c];
+      topr[0][c][lane] = mG[c];
+      topr[1][c][lane] = mT[c];
+    }
+    // output row o = r - 2: the pending combination plus its y flux
+    // difference (odeH)/(ode2H), Step 4
+    T Unew[NC], Vnew[NC], Wnew[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      Unew[c] = (T)fma(wl, (double)fprev[0][c][lane] - (double)Gn[c], pend[0][c][lane]);
+      Vnew[c] = (T)fma(wlv, (double)fprev[2][c][lane] - (double)Xn[c], pend[1][c][lane]);
+      Wnew[c] = (T)fma(wlw, (double)fprev[1][c][lane] - (double)Tn[c], pend[2][c][lane]);
+      fprev[0][c][lane] = Gn[c];
+      fprev[1][c][lane] = Tn[c];
+      fprev[2][c][lane] = Xn[c];
+    }
+    if (r >= y0 + 2 && out_col) {
+      const unsigned row = (unsigned)((r - 2) * A.nx + col);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const unsigned idx = (unsigned)(c * A.plane) + row;
+        st32(A.Uo, idx, Unew[c]);
+        st32(A.Vo, idx, Vnew[c]);
+        st32(A.Wo, idx, Wnew[c]);
       }
-      if (r >= y0 + 2) {
-        // output row o = r - 2: x-sweep of that row, then Step 4 and RK.
-        // Keep the scheduler from interleaving it with the y-work above:
-        // both working sets live at once would spill.
-        __builtin_amdgcn_sched_barrier(0);
-        const int o = r - 2;
-        double RU[NC], RV[NC], RW[NC];
-        T vt[NC];
-        sweep_x<3, IFACE>(sy, s, ax, Ua, Va, Wa, RU, RV, RW, vt);
-        if (out_col) {
-          T Unew[NC];
+      if (A.alpha_next) {
+        double sx_, sy_;
+        flag |= sy.speeds(Unew, sx_, sy_);
+        smx = fmax(smx, sx_);
+        smy = fmax(smy, sy_);
+      }
+    }
+    if (r >= y0 + 1 && r <= y1) {
+      // x-sweep of row r-1 and its RK combination without the y part.
+      // Keep the scheduler from interleaving it with the y-work above:
+      // both working sets live at once would spill.
+      __builtin_amdgcn_sched_barrier(0);
+      double RU[NC], RV[NC], RW[NC];
+      T vt[NC];
+      sweep_x<3, IFACE>(sy, s, A.pk, ax, ce, Ub, Vb, Wb, RU, RV, RW, vt);
+      if (out_col) {
+        const unsigned row = (unsigned)((r - 1) * A.nx + col);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            double Lu = RU[c] - ((double)Gn[c] - (double)fprev[0][c][lane]) * s.idy;
-            double Lv = RV[c] - ((double)Xn[c] - (double)fprev[2][c][lane]) * s.idy;
-            double Lw = RW[c] - ((double)Tn[c] - (double)fprev[1][c][lane]) * s.idy;
-            if constexpr (SOURCE) {
-              // S(X) = g (0, 0, X_0, X_2) for X = u, v, w of the stage state
-              if (c >= 2) {
-                const int k = c == 2 ? 0 : 2;
-                Lu += A.gravity * (double)Ua[k];
-                Lv += A.gravity * (double)Va[k];
-                Lw += A.gravity * (double)Wa[k];
-              }
-            }
-            const unsigned idx = (unsigned)(c * A.plane + o * A.nx + col);
-            const double ub = MODE >= kStage2 ? (double)Bu[c] : 0.0;
-            const double vb = MODE >= kStage2 ? (double)Bv[c] : 0.0;
-            const double wb = MODE >= kStage2 ? (double)Bw[c] : 0.0;
-            Unew[c] = (T)rk<MODE>((double)Ua[c], ub, dt, Lu);
-            st32(A.Uo, idx, Unew[c]);
-            st32(A.Vo, idx, (T)rk<MODE>((double)vt[c], vb, dt, Lv));
-            const T wto = topr[(r - 2) & 1][2][c][lane];   // w~ of row o
-            st32(A.Wo, idx, (T)rk<MODE>((double)wto, wb, dt, Lw));
-            if (MODE == kStage1 || MODE == kRhs) {
-              st32(A.Vt, idx, vt[c]);
-              st32(A.Wt, idx, wto);
+        for (int c = 0; c < NC; ++c) {
+          double lu = RU[c], lv = RV[c], lw = RW[c];
+          if constexpr (SOURCE) {
+            // S(X) = g (0, 0, X_0, X_2) for X = u, v, w of the stage state
+            // (v, w held times dx, dy)
+            if (c >= 2) {
+              const int k = c == 2 ? 0 : 2;
+              lu = fma(A.gravity, (double)Ub[k], lu);
+              lv = fma(A.gravity * s.idx, (double)Vb[k], lv);
+              lw = fma(A.gravity * s.idy, (double)Wb[k], lw);
             }
           }
-          if (A.alpha_next) {
-            double sx_, sy_;
-            flag |= sy.speeds(Unew, sx_, sy_);
-            smx = fmax(smx, sx_);
-            smy = fmax(smy, sy_);
+          const double ub = MODE >= kStage2 ? (double)Bu[c] : 0.0;
+          const double vb = MODE >= kStage2 ? (double)Bv[c] : 0.0;
+          const double wb = MODE >= kStage2 ? (double)Bw[c] : 0.0;
+          const double vtc = (double)vt[c] * s.idx, wtc = (double)wt[c] * s.idy;
+          pend[0][c][lane] = rk_part<MODE>((double)Ub[c], ub, dt, lu);
+          pend[1][c][lane] = rk_part<MODE>(vtc, vb, dt, lv);
+          pend[2][c][lane] = rk_part<MODE>(wtc, wb, dt, lw);
+          if (MODE == kStage1 || MODE == kRhs) {
+            const unsigned idx = (unsigned)(c * A.plane) + row;
+            st32(A.Vt, idx, (T)vtc);
+            st32(A.Wt, idx, (T)wtc);
           }
         }
       }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        fprev[0][c][lane] = Gn[c];
-        fprev[1][c][lane] = Tn[c];
-        fprev[2][c][lane] = Xn[c];
-      }
     }
-    // rotate the ring
+    // rotate the registers
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      if (r < y0 + 1) {
-        ring[slot][0][c][lane] = gc[c];
-        ring[slot][1][c][lane] = tc[c];
-        ring[slot][2][c][lane] = xc[c];
-      }
       Ua[c] = Ub[c]; Ub[c] = Uc[c];
-      Va[c] = Vb[c]; Vb[c] = Vc[c];
       Wa[c] = Wb[c]; Wb[c] = Wc[c];
+      Vb[c] = Vc[c];
+      if (MODE >= kStage2) { Bu[c] = Bun[c]; Bv[c] = Bvn[c]; Bw[c] = Bwn[c]; }
     }
     slot = slot == 2 ? 0 : slot + 1;
   }
@@ -595,61 +789,22 @@ __global__ __launch_bounds__(256) void alpha_out_kernel(const double* partial, i
   if (threadIdx.x == 0) { alpha[0] = ax; alpha[1] = ay; }
 }
 
-// Workspace scalars of one time step.
-struct StepScalars {
-  double alpha1[2];               // stage-1 alphas
-  unsigned long long acc[4];      // stage-2 and stage-3 alphas (atomic max bits)
-  double dt;
-  double t0;                      // the step's start time
-  int active;
-  unsigned flags;
-};
-
-// Delta t of the step from the stage-1 alphas (a2), clipped to t_end; also
-// arms the stage-2/3 alpha accumulators.
-struct DtArgs {
-  int rule;
-  double cfl, dt_fixed, t_end;
-  double hx, hy;   // dx, dy (production) or dx^(5/3), dy^(5/3) (accuracy)
-  int dim;
-};
-
-__global__ __launch_bounds__(256) void dt_kernel(const double* partial, int n, DtArgs a,
-                                                 StepScalars* sc, double* t, double* dt_used,
-                                                 double* alpha_rec) {
+// Seeds a run of steps (a2): reduces the per-block maxima of the state's
+// spectral radii into the next-step accumulators (the stage-1 alphas of the
+// first step) and clears the stage-2 and stage-3 accumulators.
+__global__ __launch_bounds__(256) void alpha_seed_kernel(const double* partial, int n,
+                                                         StepScalars* sc) {
   double ax, ay;
   reduce_partials(partial, n, &ax, &ay);
   if (threadIdx.x != 0) return;
-  if (a.dim == 1) ay = 0.0;
-  sc->alpha1[0] = ax;
-  sc->alpha1[1] = ay;
+  sc->acc[4] = (unsigned long long)__double_as_longlong(ax);
+  sc->acc[5] = (unsigned long long)__double_as_longlong(ay);
   for (int k = 0; k < 4; ++k) sc->acc[k] = 0ull;
-  if (alpha_rec) { alpha_rec[0] = ax; alpha_rec[1] = ay; }
-  double dt;
-  if (a.rule == HWENO_DT_FIXED) dt = a.dt_fixed;
-  else dt = a.cfl / (a.dim == 2 ? ax / a.hx + ay / a.hy : ax / a.hx);
-  const double t0 = *t;
-  sc->t0 = t0;
-  int active = t0 < a.t_end ? 1 : 0;
-  if (active) {
-    if (t0 + dt >= a.t_end) {
-      dt = a.t_end - t0;
-      *t = a.t_end;
-    } else {
-      *t = t0 + dt;
-    }
-  } else {
-    dt = 0.0;
-  }
-  sc->dt = dt;
-  sc->active = active;
-  if (dt_used) *dt_used = dt;
 }
 
 __global__ void ws_init_kernel(StepScalars* sc) {
-  sc->alpha1[0] = sc->alpha1[1] = 0.0;
-  for (int k = 0; k < 4; ++k) sc->acc[k] = 0ull;
-  sc->dt = 0.0;
+  for (int k = 0; k < 6; ++k) sc->acc[k] = 0ull;
+  sc->dt = sc->t0 = sc->tnew = 0.0;
   sc->active = 0;
   sc->flags = 0u;
 }
@@ -1258,6 +1413,10 @@ constexpr int kPartialBlocks = 1024;
 constexpr size_t kPartialBytes = kPartialBlocks * 2 * sizeof(double);
 constexpr int kRowsPerBlock = 32;
 
+// Strip height of the 2D forward stage kernels set by hweno_set_strip_rows
+// (0: chosen by the occupancy model).
+std::atomic<int> g_strip_rows{0};
+
 struct Geometry {
   int nc, nf;           // components; fields per state (2 in 1D: u, v; 3 in 2D)
   size_t esize;         // element size
@@ -1527,7 +1686,9 @@ hweno_status launch_stage(int mode, const StageArgs<T>& A0, const Sys& sy, hipSt
       const bool known = occupancy<decltype(tag)::value, kWave>(kernel, &per_cu, &cus);
       // warm-up: two rows of loads and y-pointwise fluxes, two of y-HWENO,
       // about one full row in all
-      A.rows = balanced_rows((A.nx + kXOut - 1) / kXOut, A.ny, known, per_cu, cus, 1.0, 32);
+      const int forced = g_strip_rows.load(std::memory_order_relaxed);
+      A.rows = forced > 0 ? forced
+                          : balanced_rows((A.nx + kXOut - 1) / kXOut, A.ny, known, per_cu, cus, 1.0, 32);
       dim3 grid((A.nx + kXOut - 1) / kXOut, (A.ny + A.rows - 1) / A.rows);
       kernel<<<grid, kWave, 0, st>>>(A, sy);
     };
@@ -1590,7 +1751,9 @@ StageArgs<T> base_args(const hweno_problem* p) {
   }
   A.t0 = nullptr;
   A.tc = 0.0;
+  A.ctl.dim = p->dim;
   A.s = make_scheme(p);
+  A.pk = point_k(A.s);
   return A;
 }
 
@@ -1779,6 +1942,104 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   return HWENO_OK;
 }
 
+// Time-stepping loop of hweno_step(s) (a2, a10): one seeding pass (per-block
+// maxima of the spectral radii of the initial state, reduced into the
+// stage-1 alphas), then three stage launches per step. Stage 1 computes the
+// step's dt from its alphas, stage 3 reduces the next step's stage-1 alphas
+// in its epilogue, so steady-state steps launch the three stage kernels only.
+hweno_status run_steps(const hweno_problem* p, void* u, void* v, void* w, int32_t nsteps,
+                       int32_t dt_rule, double cfl, double dt_fixed, double t_end, double* t,
+                       double* dt_used, double* alpha_rec, void* stages, void* ws,
+                       hipStream_t stream, hipEvent_t* events) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (!u || !v || !t || !ws || nsteps < 1) return HWENO_EINVAL;
+  if (p->dim == 2 && !w) return HWENO_EINVAL;
+  if (p->dim == 1 && w) return HWENO_EINVAL;
+  if (dt_rule < HWENO_DT_PRODUCTION || dt_rule > HWENO_DT_FIXED) return HWENO_EINVAL;
+  if (dt_rule == HWENO_DT_FIXED ? !(dt_fixed > 0.0) : !(cfl > 0.0)) return HWENO_EINVAL;
+  if (std::isnan(t_end)) return HWENO_EINVAL;
+  if (stages && nsteps != 1) return HWENO_EINVAL;
+  const Geometry g = geometry(p);
+  WsLayout wl = ws_layout(p, ws, g);
+  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
+    using T = decltype(tag);
+    using Sys = decltype(sy);
+    constexpr int DIM = decltype(dimc)::value;
+    const size_t P = g.plane;
+    // stage states: the caller's `stages` buffer when given, else the workspace
+    char* x1 = stages ? (char*)stages : wl.x1;
+    char* x2 = stages ? (char*)stages + (size_t)g.nf * g.nc * P * sizeof(T) : wl.x2;
+    T* Vt = (T*)wl.base;
+    T* Wt = DIM == 2 ? Vt + (size_t)g.nc * P : nullptr;
+    auto F = [&](char* b, int f) { return (T*)(b + (size_t)f * g.nc * P * sizeof(T)); };
+    int nb;
+    hweno_status s2 = launch_speed_partial<Sys, T, DIM>(p, (const T*)u, sy, wl.partial,
+                                                        &wl.sc->flags, stream, &nb);
+    if (s2 != HWENO_OK) return s2;
+    alpha_seed_kernel<<<1, 256, 0, stream>>>(wl.partial, nb, wl.sc);
+    if ((s2 = check_launch()) != HWENO_OK) return s2;
+    StageArgs<T> A = base_args<T>(p);
+    A.dt = &wl.sc->dt;
+    A.active = &wl.sc->active;
+    A.flags = &wl.sc->flags;
+    A.t0 = &wl.sc->t0;            // stage times t0, t0 + dt, t0 + dt/2
+    A.ctl.sc = wl.sc;
+    A.ctl.t = t;
+    A.ctl.rule = dt_rule;
+    A.ctl.cfl = cfl;
+    A.ctl.dt_fixed = dt_fixed;
+    A.ctl.t_end = t_end;
+    if (dt_rule == HWENO_DT_ACCURACY) {
+      A.ctl.hx = std::pow(p->dx, 5.0 / 3.0);
+      A.ctl.hy = DIM == 2 ? std::pow(p->dy, 5.0 / 3.0) : 1.0;
+    } else {
+      A.ctl.hx = p->dx;
+      A.ctl.hy = DIM == 2 ? p->dy : 1.0;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+      hipEvent_t* ev = events ? events + 4 * k : nullptr;
+      auto mark = [&](int j) -> bool { return !ev || hipEventRecord(ev[j], stream) == hipSuccess; };
+      double* rec = alpha_rec ? alpha_rec + 6 * k : nullptr;
+      A.ctl.dt_used = dt_used ? dt_used + k : nullptr;
+      // stage 1: X^n -> X^(1), V~^n, W~^n; computes dt
+      if (!mark(0)) return HWENO_EDEVICE;
+      A.U = (const T*)u; A.V = (const T*)v; A.W = (const T*)w;
+      A.Ub = nullptr; A.Vb = nullptr; A.Wb = nullptr;
+      A.Uo = F(x1, 0); A.Vo = F(x1, 1); A.Wo = DIM == 2 ? F(x1, 2) : nullptr;
+      A.Vt = Vt; A.Wt = Wt;
+      A.alpha = (const double*)&wl.sc->acc[4];
+      A.alpha_next = &wl.sc->acc[0];
+      A.alpha_rec = rec;
+      A.tc = 0.0;
+      if ((s2 = launch_stage<Sys, T, DIM>(kStage1, A, sy, stream)) != HWENO_OK) return s2;
+      if (!mark(1)) return HWENO_EDEVICE;
+      // stage 2: X^(1) -> X^(2) with base (U^n, V~^n, W~^n)
+      A.U = F(x1, 0); A.V = F(x1, 1); A.W = DIM == 2 ? F(x1, 2) : nullptr;
+      A.Ub = (const T*)u; A.Vb = Vt; A.Wb = Wt;
+      A.Uo = F(x2, 0); A.Vo = F(x2, 1); A.Wo = DIM == 2 ? F(x2, 2) : nullptr;
+      A.Vt = nullptr; A.Wt = nullptr;
+      A.alpha = (const double*)&wl.sc->acc[0];
+      A.alpha_next = &wl.sc->acc[2];
+      A.alpha_rec = rec ? rec + 2 : nullptr;
+      A.tc = 1.0;
+      if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
+      if (!mark(2)) return HWENO_EDEVICE;
+      // stage 3: X^(2) -> X^{n+1}, in place on (u, v, w); the result's alphas
+      // are the next step's stage-1 alphas
+      A.U = F(x2, 0); A.V = F(x2, 1); A.W = DIM == 2 ? F(x2, 2) : nullptr;
+      A.Uo = (T*)u; A.Vo = (T*)v; A.Wo = (T*)w;
+      A.alpha = (const double*)&wl.sc->acc[2];
+      A.alpha_next = &wl.sc->acc[4];
+      A.alpha_rec = rec ? rec + 4 : nullptr;
+      A.tc = 0.5;
+      if ((s2 = launch_stage<Sys, T, DIM>(kStage3, A, sy, stream)) != HWENO_OK) return s2;
+      if (!mark(3)) return HWENO_EDEVICE;
+    }
+    return HWENO_OK;
+  });
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1862,95 +2123,30 @@ hweno_status hweno_rhs(const hweno_problem* p, const void* u, const void* v, con
 hweno_status hweno_step(const hweno_problem* p, void* u, void* v, void* w, int32_t dt_rule,
                         double cfl, double dt_fixed, double t_end, double* t, double* dt_used,
                         double* alpha_rec, void* stages, void* ws, hipStream_t stream) {
-  return hweno_step_profiled(p, u, v, w, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec,
-                             stages, ws, stream, nullptr);
+  return run_steps(p, u, v, w, 1, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec, stages, ws,
+                   stream, nullptr);
 }
 
 hweno_status hweno_step_profiled(const hweno_problem* p, void* u, void* v, void* w,
                                  int32_t dt_rule, double cfl, double dt_fixed, double t_end,
                                  double* t, double* dt_used, double* alpha_rec, void* stages,
                                  void* ws, hipStream_t stream, hipEvent_t* events) {
-  hweno_status st = validate(p);
-  if (st != HWENO_OK) return st;
-  if (!u || !v || !t || !ws) return HWENO_EINVAL;
-  if (p->dim == 2 && !w) return HWENO_EINVAL;
-  if (p->dim == 1 && w) return HWENO_EINVAL;
-  if (dt_rule < HWENO_DT_PRODUCTION || dt_rule > HWENO_DT_FIXED) return HWENO_EINVAL;
-  if (dt_rule == HWENO_DT_FIXED ? !(dt_fixed > 0.0) : !(cfl > 0.0)) return HWENO_EINVAL;
-  if (std::isnan(t_end)) return HWENO_EINVAL;
-  const Geometry g = geometry(p);
-  WsLayout wl = ws_layout(p, ws, g);
-  return dispatch(p, [&](auto sy, auto tag, auto dimc) -> hweno_status {
-    using T = decltype(tag);
-    using Sys = decltype(sy);
-    constexpr int DIM = decltype(dimc)::value;
-    const size_t P = g.plane;
-    // stage states: the caller's `stages` buffer when given, else the workspace
-    char* x1 = stages ? (char*)stages : wl.x1;
-    char* x2 = stages ? (char*)stages + (size_t)g.nf * g.nc * P * sizeof(T) : wl.x2;
-    T* Vt = (T*)wl.base;
-    T* Wt = DIM == 2 ? Vt + (size_t)g.nc * P : nullptr;
-    auto F = [&](char* b, int f) { return (T*)(b + (size_t)f * g.nc * P * sizeof(T)); };
-    // stage-1 alphas and dt
-    int nb;
-    hweno_status s2 = launch_speed_partial<Sys, T, DIM>(p, (const T*)u, sy, wl.partial,
-                                                        &wl.sc->flags, stream, &nb);
-    if (s2 != HWENO_OK) return s2;
-    DtArgs da;
-    da.rule = dt_rule;
-    da.cfl = cfl;
-    da.dt_fixed = dt_fixed;
-    da.t_end = t_end;
-    da.dim = DIM;
-    if (dt_rule == HWENO_DT_ACCURACY) {
-      da.hx = std::pow(p->dx, 5.0 / 3.0);
-      da.hy = DIM == 2 ? std::pow(p->dy, 5.0 / 3.0) : 1.0;
-    } else {
-      da.hx = p->dx;
-      da.hy = DIM == 2 ? p->dy : 1.0;
-    }
-    dt_kernel<<<1, 256, 0, stream>>>(wl.partial, nb, da, wl.sc, t, dt_used, alpha_rec);
-    if ((s2 = check_launch()) != HWENO_OK) return s2;
-    StageArgs<T> A = base_args<T>(p);
-    A.dt = &wl.sc->dt;
-    A.active = &wl.sc->active;
-    A.flags = &wl.sc->flags;
-    A.t0 = &wl.sc->t0;            // stage times t0, t0 + dt, t0 + dt/2
-    auto mark = [&](int k) -> bool {
-      return !events || hipEventRecord(events[k], stream) == hipSuccess;
-    };
-    // stage 1: X^n -> X^(1), V~^n, W~^n
-    if (!mark(0)) return HWENO_EDEVICE;
-    A.U = (const T*)u; A.V = (const T*)v; A.W = (const T*)w;
-    A.Uo = F(x1, 0); A.Vo = F(x1, 1); A.Wo = DIM == 2 ? F(x1, 2) : nullptr;
-    A.Vt = Vt; A.Wt = Wt;
-    A.alpha = wl.sc->alpha1;
-    A.alpha_next = &wl.sc->acc[0];
-    A.alpha_rec = nullptr;
-    if ((s2 = launch_stage<Sys, T, DIM>(kStage1, A, sy, stream)) != HWENO_OK) return s2;
-    if (!mark(1)) return HWENO_EDEVICE;
-    // stage 2: X^(1) -> X^(2) with base (U^n, V~^n, W~^n)
-    A.U = F(x1, 0); A.V = F(x1, 1); A.W = DIM == 2 ? F(x1, 2) : nullptr;
-    A.Ub = (const T*)u; A.Vb = Vt; A.Wb = Wt;
-    A.Uo = F(x2, 0); A.Vo = F(x2, 1); A.Wo = DIM == 2 ? F(x2, 2) : nullptr;
-    A.Vt = nullptr; A.Wt = nullptr;
-    A.alpha = (const double*)&wl.sc->acc[0];
-    A.alpha_next = &wl.sc->acc[2];
-    A.alpha_rec = alpha_rec ? alpha_rec + 2 : nullptr;
-    A.tc = 1.0;
-    if ((s2 = launch_stage<Sys, T, DIM>(kStage2, A, sy, stream)) != HWENO_OK) return s2;
-    if (!mark(2)) return HWENO_EDEVICE;
-    // stage 3: X^(2) -> X^{n+1}, in place on (u, v, w)
-    A.U = F(x2, 0); A.V = F(x2, 1); A.W = DIM == 2 ? F(x2, 2) : nullptr;
-    A.Uo = (T*)u; A.Vo = (T*)v; A.Wo = (T*)w;
-    A.alpha = (const double*)&wl.sc->acc[2];
-    A.alpha_next = nullptr;
-    A.alpha_rec = alpha_rec ? alpha_rec + 4 : nullptr;
-    A.tc = 0.5;
-    if ((s2 = launch_stage<Sys, T, DIM>(kStage3, A, sy, stream)) != HWENO_OK) return s2;
-    if (!mark(3)) return HWENO_EDEVICE;
-    return HWENO_OK;
-  });
+  return run_steps(p, u, v, w, 1, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec, stages, ws,
+                   stream, events);
+}
+
+hweno_status hweno_steps(const hweno_problem* p, void* u, void* v, void* w, int32_t nsteps,
+                         int32_t dt_rule, double cfl, double dt_fixed, double t_end, double* t,
+                         double* dt_used, double* alpha_rec, void* ws, hipStream_t stream,
+                         hipEvent_t* events) {
+  return run_steps(p, u, v, w, nsteps, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec,
+                   nullptr, ws, stream, events);
+}
+
+hweno_status hweno_set_strip_rows(int32_t rows) {
+  if (rows < 0) return HWENO_EINVAL;
+  g_strip_rows.store(rows, std::memory_order_relaxed);
+  return HWENO_OK;
 }
 
 hweno_status hweno_step_frozen(const hweno_problem* p, void* u, void* v, void* w, void* u_out,

@@ -60,6 +60,10 @@ _SIGS = {
     'hweno_step_profiled': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P],
                             ctypes.c_int),
+    'hweno_steps': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P],
+                    ctypes.c_int),
+    'hweno_set_strip_rows': ([ctypes.c_int32], ctypes.c_int),
     'hweno_step_frozen': ([ctypes.POINTER(_CProblem)] + [_P] * 11, ctypes.c_int),
     'hweno_adjoint_step': ([ctypes.POINTER(_CProblem)] + [_P] * 14, ctypes.c_int),
     'hweno_health': ([ctypes.POINTER(_CProblem), _P, _P, ctypes.c_int32], ctypes.c_int),
@@ -83,6 +87,12 @@ def load_library(path=LIB_PATH):
             fn.restype = res
         _lib = lib
     return _lib
+
+
+def set_strip_rows(rows):
+    """Force the strip height of the 2D forward stage kernels (0: automatic);
+    results do not depend on it. Process-wide."""
+    _check(load_library().hweno_set_strip_rows(int(rows)), 'hweno_set_strip_rows')
 
 
 def _check(code, what):
@@ -256,6 +266,27 @@ class Solver:
         else:
             _check(self.lib.hweno_step_profiled(*args, events), 'hweno_step_profiled')
 
+    def steps(self, U, V, W, t, nsteps, t_end=float('inf'), rule='production', cfl=0.6,
+              dt_fixed=0.0, dt_used=None, alpha_rec=None, events=None):
+        """``nsteps`` SSP-RK3 steps in place (hweno_steps): the stage-1 alphas
+        of every step after the first come from the previous step's last
+        stage. ``dt_used`` / ``alpha_rec``: optional float64 device tensors of
+        nsteps / nsteps x 6 values; ``events``: optional ctypes array of
+        4 * nsteps hipEvent_t."""
+        two = self.prob.dim == 2
+        U, V = self._state(U, 'U'), self._state(V, 'V')
+        W = self._state(W, 'W') if two else None
+        nsteps = int(nsteps)
+        for name, x, n in (('t', t, 1), ('dt_used', dt_used, nsteps),
+                           ('alpha_rec', alpha_rec, 6 * nsteps)):
+            if x is not None and not (x.dtype == torch.float64 and x.device.type == 'cuda'
+                                      and x.numel() >= n and x.is_contiguous()):
+                raise ValueError(f'{name} must be a contiguous float64 device tensor of {n} values')
+        _check(self.lib.hweno_steps(ctypes.byref(self.cp), _ptr(U), _ptr(V), _ptr(W), nsteps,
+                                    DT_RULES[rule], float(cfl), float(dt_fixed), float(t_end),
+                                    _ptr(t), _ptr(dt_used), _ptr(alpha_rec), _ptr(self.ws),
+                                    _stream(self.device), events), 'hweno_steps')
+
     def _stages_ok(self, stages):
         if stages is None:
             return None
@@ -319,10 +350,11 @@ class Solver:
         chunks; the device skips steps once t reaches t_end. Returns
         (steps, t, dts[, alpha_recs]) with dts / alphas as device tensors.
 
-        graph=True captures one chunk of steps as a HIP graph and replays it
-        (one graph launch per chunk instead of five kernel launches per
-        step): for sizes where launch overhead, not the kernels, sets the
-        pace. The results are the same bit for bit."""
+        Each chunk is one hweno_steps call: two seeding launches, then the
+        three stage kernels per step. graph=True captures one chunk as a HIP
+        graph and replays it (one graph launch per chunk): for sizes where
+        launch overhead, not the kernels, sets the pace. The results are the
+        same bit for bit."""
         t = torch.zeros(1, dtype=torch.float64, device=self.device)
         cap = max_steps if max_steps is not None else 1 << 30
         dts, recs = [], []
@@ -332,15 +364,13 @@ class Solver:
             # one step on copies first: the launch code's one-time queries
             # (occupancy) then stay out of the capture
             c = lambda x: None if x is None else x.clone()
-            self.step(c(U), c(V), c(W), c(t), t_end, rule, cfl)
+            self.steps(c(U), c(V), c(W), c(t), 1, t_end, rule, cfl)
             gbuf = torch.zeros(chunk, dtype=torch.float64, device=self.device)
             grec = torch.zeros(chunk, 6, dtype=torch.float64, device=self.device) if record else None
             torch.cuda.synchronize(self.device)
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                for j in range(chunk):
-                    self.step(U, V, W, t, t_end, rule, cfl, dt_used=gbuf[j:j + 1],
-                              alpha_rec=grec[j] if record else None)
+                self.steps(U, V, W, t, chunk, t_end, rule, cfl, dt_used=gbuf, alpha_rec=grec)
         while n < cap:
             k = min(chunk, cap - n)
             if g is not None and k == chunk:
@@ -351,9 +381,7 @@ class Solver:
             else:
                 buf = torch.zeros(k, dtype=torch.float64, device=self.device)
                 rec = torch.zeros(k, 6, dtype=torch.float64, device=self.device) if record else None
-                for j in range(k):
-                    self.step(U, V, W, t, t_end, rule, cfl, dt_used=buf[j:j + 1],
-                              alpha_rec=rec[j] if record else None)
+                self.steps(U, V, W, t, k, t_end, rule, cfl, dt_used=buf, alpha_rec=rec)
             dts.append(buf)
             if record:
                 recs.append(rec)

@@ -267,16 +267,23 @@ def euler1d_riemann_sine(n=2000, seed=2000, g=1.4):
                     extra=dict(jumps=pos, A=A, m=m))
 
 
-def _fourier_field(rng, X, Y, modes=16, kmax=8):
+def _fourier_field(rng, X, Y, modes=16, kmax=8, yscale=1.0):
     """Sum of ``modes`` waves sin(pi (kx x + ky y) + theta), 1 <= max|k| <=
     kmax, normalised to max |value| = 1 over the grid; returns the field and
-    its exact x- and y-derivatives (same normalisation)."""
+    its exact x- and y-derivatives (same normalisation). kx is an integer;
+    ky = j yscale with an integer j (yscale = 1: integers), which makes every
+    wave periodic on a y-period of 2 / yscale."""
     f = np.zeros_like(X)
     fx = np.zeros_like(X)
     fy = np.zeros_like(X)
+    jmax = int(math.floor(kmax / yscale + 1e-12))
     for _ in range(modes):
         while True:
-            kx, ky = rng.integers(-kmax, kmax + 1, size=2)
+            if yscale == 1.0:
+                kx, ky = rng.integers(-kmax, kmax + 1, size=2)
+            else:
+                kx, j = rng.integers(-kmax, kmax + 1), rng.integers(-jmax, jmax + 1)
+                ky = j * yscale
             if max(abs(kx), abs(ky)) >= 1:
                 break
         th = rng.uniform(0.0, 2.0 * math.pi)
@@ -291,15 +298,18 @@ def _fourier_field(rng, X, Y, modes=16, kmax=8):
 
 def euler2d_smooth(n, seed=3000, g=1.4, amp=0.2, ny=None):
     """[0,2]^2 periodic; rho = 1 + amp phi_r, u = amp phi_u, v = amp phi_v,
-    p = 1; each phi a seeded sum of 16 Fourier modes with max|k| <= 8."""
+    p = 1; each phi a seeded sum of 16 Fourier modes with max|k| <= 8.
+    With ny != n the domain is [0,2] x [0, 2 ny/n] (dy = dx) and the
+    y-wavenumbers are multiples of n/ny, so every mode is periodic on it."""
     ny = n if ny is None else ny
     rng = np.random.default_rng(seed)
     x, hx = centres(n, 0.0, 2.0)
     y, hy = centres(ny, 0.0, 2.0 * ny / n)
     X, Y = np.meshgrid(x, y)
-    fr, frx, fry = _fourier_field(rng, X, Y)
-    fu, fux, fuy = _fourier_field(rng, X, Y)
-    fv, fvx, fvy = _fourier_field(rng, X, Y)
+    ys = n / ny
+    fr, frx, fry = _fourier_field(rng, X, Y, yscale=ys)
+    fu, fux, fuy = _fourier_field(rng, X, Y, yscale=ys)
+    fv, fvx, fvy = _fourier_field(rng, X, Y, yscale=ys)
     rho, u, v = 1.0 + amp * fr, amp * fu, amp * fv
     p = np.ones_like(X)
     zero = np.zeros_like(X)

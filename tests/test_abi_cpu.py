@@ -172,3 +172,22 @@ def test_frozen_step_output_checks(lib):
     assert f(ctypes.byref(p), u, v, w, a[6], None, a[7], dt, rec, None, ws, None) == -1
     assert f(ctypes.byref(p), u, v, w, a[6], a[7], None, dt, rec, None, ws, None) == -1
     assert f(ctypes.byref(p), u, v, w, None, a[6], None, dt, rec, None, ws, None) == -1
+
+
+def test_multi_step_and_strip_setting_validation(lib):
+    """hweno_steps rejects a non-positive step count and null buffers before
+    launching anything; hweno_set_strip_rows accepts 0 (automatic) and
+    positive heights, rejects negative ones."""
+    p = _prob()
+    a = [ctypes.c_void_p(0x1000 * (k + 1)) for k in range(5)]
+    u, v, w, t, ws = a
+    f = lib.hweno_steps
+    assert f(ctypes.byref(p), u, v, w, 0, 0, 0.6, 0.0, 1.0, t, None, None, ws, None, None) == -1
+    assert f(ctypes.byref(p), u, v, w, -3, 0, 0.6, 0.0, 1.0, t, None, None, ws, None, None) == -1
+    assert f(ctypes.byref(p), None, v, w, 4, 0, 0.6, 0.0, 1.0, t, None, None, ws, None, None) == -1
+    assert f(ctypes.byref(p), u, v, w, 4, 0, 0.6, 0.0, 1.0, None, None, None, ws, None, None) == -1
+    assert f(ctypes.byref(p), u, v, w, 4, 9, 0.6, 0.0, 1.0, t, None, None, ws, None, None) == -1
+    assert lib.hweno_set_strip_rows(-1) == -1
+    assert lib.hweno_set_strip_rows(7) == 0
+    assert lib.hweno_set_strip_rows(0) == 0
+

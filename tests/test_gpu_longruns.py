@@ -1,0 +1,106 @@
+"""Long 2D Euler runs on the GPU against the FP64 oracle's full runs
+(2Dfully-hweno, production time step from the stage-1 alphas each step).
+
+Expected values: ``tests/golden/long_runs.npz``, written by
+``tests/golden/make_long_runs.py`` from the oracle alone (its final fields,
+step counts, time steps, and its divergence from itself under one-ulp and
+one-FP32-ulp perturbations of every input value).
+
+* quadrants_128: the four-quadrant Riemann data (seed 4000, 128^2,
+  transmissive) to T = 0.25;
+* smooth_256: the smooth periodic data (seed 3000, 256^2), 100 steps.
+
+Bounds. FP64: the nonlinear weights amplify round-off (the oracle differs
+from itself by far more than 1e-12 after these runs when its inputs move by
+one ulp), so each field must lie within 10x the oracle's one-ulp divergence
+(at least 1e-12); the step count must match exactly, the time steps and
+the end time to the same relative bound as U (at least 1e-14). FP32: the run stores every state in
+float, i.e. perturbs it by up to one FP32 ulp per stage; the error is
+stated per field against the FP64 oracle. Where the oracle responds
+linearly to perturbations (its FP32-ulp divergence is at least 2^20 times
+its one-ulp divergence: the smooth run), the bound is the number of stages
+times the FP32-ulp divergence (one such perturbation per stage, added up);
+where the response is saturated (both divergences alike: the shock run,
+whose nonlinear weights turn any rounding difference into the same
+O(1e-3) change), it is 10x the FP32-ulp divergence.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2411_11229_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), 'golden', 'long_runs.npz')
+
+RUNS = {
+    'quadrants_128': (lambda: WL.euler2d_quadrants(128, seed=4000), 0.25, None),
+    'smooth_256': (lambda: WL.euler2d_smooth(256, seed=3000), 1e9, 100),
+}
+
+
+def H():
+    from paper_2411_11229_amd import hweno
+    return hweno
+
+
+@pytest.fixture(scope='module')
+def gold():
+    return np.load(GOLD)
+
+
+def run_gpu(name, precision):
+    h = H()
+    mk, t_end, max_steps = RUNS[name]
+    w = mk()
+    dtype = torch.float64 if precision == 'f64' else torch.float32
+    s = h.Solver(h.Problem(**w.problem_kwargs(), precision=precision))
+    d = lambda a: torch.tensor(a, dtype=dtype, device='cuda')
+    U, V, W = d(w.U), d(w.V), d(w.W)
+    steps, t, dts = s.run(U, V, W, t_end=t_end, max_steps=max_steps)
+    s.health()
+    host = lambda x: x.double().cpu().numpy()
+    return steps, t, host(dts), (host(U), host(V), host(W))
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_long_run_f64_matches_oracle(name, gold):
+    print(f'run {name} f64', flush=True)
+    steps, t, dts, fields = run_gpu(name, 'f64')
+    div = gold[f'{name}_ulp_divergence']
+    assert steps == int(gold[f'{name}_steps'])
+    # the end time is the sum of the time steps (exact where the last step
+    # was clipped to T)
+    assert t == pytest.approx(float(gold[f'{name}_t']), rel=max(10 * div[0], 1e-14))
+    np.testing.assert_allclose(dts, gold[f'{name}_dts'], rtol=max(10 * div[0], 1e-12))
+    for k, (g, key) in enumerate(zip(fields, 'UVW')):
+        e = rel(g, gold[f'{name}_{key}'])
+        bound = max(10.0 * div[k], 1e-12)
+        print(f'  {key}: rel err {e:.3e}  oracle one-ulp divergence {div[k]:.3e}', flush=True)
+        assert e <= bound, f'{name} {key}: rel err {e:.3e} > {bound:.3e}'
+
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_long_run_f32_error_against_oracle(name, gold):
+    print(f'run {name} f32', flush=True)
+    steps, t, dts, fields = run_gpu(name, 'f32')
+    n64 = int(gold[f'{name}_steps'])
+    assert abs(steps - n64) <= max(1, n64 // 100)
+    assert t == pytest.approx(float(gold[f'{name}_t']), rel=1e-3)
+    f32div = gold[f'{name}_f32ulp_divergence']
+    div = gold[f'{name}_ulp_divergence']
+    stages = 3 * n64
+    for k, (g, key) in enumerate(zip(fields, 'UVW')):
+        e = rel(g, gold[f'{name}_{key}'])
+        linear = f32div[k] >= 2.0 ** 20 * div[k]
+        bound = stages * f32div[k] if linear else 10.0 * f32div[k]
+        print(f'  {key}: FP32 rel err vs FP64 oracle {e:.3e}  (oracle FP32-ulp divergence '
+              f'{f32div[k]:.3e}, bound {bound:.3e})', flush=True)
+        assert e <= bound, f'{name} {key}: FP32 rel err {e:.3e} > {bound:.3e}'

@@ -1,0 +1,92 @@
+"""The benchmark workload (2D Euler, 2048^2 four-quadrant Riemann data, seed
+4000, transmissive) in the benchmark's launch configuration, compared with
+the FP64 oracle over the WHOLE field (every cell and component):
+
+* FP64: one operator evaluation (odeH)/(ode2H) with the modified
+  derivatives (limiter), and one SSP-RK3 step (2Dfully-hweno) with its time
+  step and stage alphas, within 1e-12 of each output's max;
+* FP32: one operator evaluation within the bounds derived from the FP32
+  arithmetic (f32_bounds in test_gpu_parity.py), on float-rounded inputs.
+
+The oracle runs on torch-CPU in float64 (the same oracle source as the NumPy
+runs) with the host's threads, which takes about a minute per step here.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hweno as O
+from paper_2411_11229_amd import workloads as WL
+
+from test_gpu_parity import RTOL64, dev, f32_bounds, host, oprob, rel_err, solver
+
+pytestmark = pytest.mark.gpu
+
+
+def _cpu_threads():
+    torch.set_num_threads(max(1, min(16, os.cpu_count() or 1)))
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a))
+
+
+def _np(x):
+    return None if x is None else (x.numpy() if isinstance(x, torch.Tensor) else x)
+
+
+@pytest.mark.timeout(600)
+def test_operator_and_step_2048_whole_field_f64():
+    _cpu_threads()
+    w = WL.euler2d_quadrants(2048, seed=4000)
+    p = oprob(w)
+    alpha = O.max_speed(p, w.U)
+    s = solver(w)
+    U, V, W = dev(w.U), dev(w.V), dev(w.W)
+    print('operator', flush=True)
+    got = [host(x) for x in s.rhs(U, V, W, dev(np.array(alpha)))]
+    ref = [_np(x) for x in O.rhs(p, _t(w.U), _t(w.V), _t(w.W), alpha)]
+    names = ('L1', 'L2', 'L3', 'vtilde', 'wtilde')
+    for name, g, r in zip(names, got, ref):
+        e = rel_err(g, r)
+        print(f'  {name}: rel err {e:.3e}', flush=True)
+        assert e <= RTOL64, f'{name}: rel err {e:.3e}'
+    del got, ref
+    print('step', flush=True)
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dt_used = torch.zeros(1, dtype=torch.float64, device='cuda')
+    rec = torch.zeros(6, dtype=torch.float64, device='cuda')
+    s.step(U, V, W, t, w.t_end, dt_used=dt_used, alpha_rec=rec)
+    dt = O.time_step(p, alpha, 'production', 0.6)
+    U3, V3, W3, als = O.step(p, _t(w.U), _t(w.V), _t(w.W), dt)
+    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-14)
+    r = host(rec).reshape(3, 2)
+    for k in range(3):
+        np.testing.assert_allclose(r[k], np.array(als[k], dtype=float)[:2], rtol=1e-12)
+    for name, g, ref in (('U', U, U3), ('V', V, V3), ('W', W, W3)):
+        e = rel_err(host(g), _np(ref))
+        print(f'  {name}: rel err {e:.3e}', flush=True)
+        assert e <= RTOL64, f'{name}: rel err {e:.3e}'
+    s.health()
+
+
+@pytest.mark.timeout(600)
+def test_operator_2048_whole_field_f32():
+    _cpu_threads()
+    w = WL.euler2d_quadrants(2048, seed=4000)
+    for k in ('U', 'V', 'W'):
+        setattr(w, k, getattr(w, k).astype(np.float32).astype(np.float64))
+    p = oprob(w)
+    alpha = O.max_speed(p, w.U)
+    s = solver(w, precision='f32')
+    f32 = lambda a: dev(a, torch.float32)
+    got = [host(x) for x in s.rhs(f32(w.U), f32(w.V), f32(w.W), dev(np.array(alpha)))]
+    ref = [_np(x) for x in O.rhs(p, _t(w.U), _t(w.V), _t(w.W), alpha)]
+    tol = f32_bounds(w, alpha)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = float(np.max(np.abs(g - r)))
+        print(f'  output {k}: abs err {err:.3e}  bound {tol[k]:.3e}  rel {err / np.max(np.abs(r)):.2e}',
+              flush=True)
+        assert err <= tol[k], f'output {k}: abs err {err:.3e} > bound {tol[k]:.3e}'
