@@ -52,7 +52,8 @@ typedef enum {
   HWENO_EUNSUPPORTED = -2,   /* valid but not implemented combination           */
   HWENO_EDEVICE = -3,        /* a HIP runtime call failed                        */
   HWENO_ENONFINITE = -4,     /* a NaN / Inf was seen in a state                  */
-  HWENO_ENONPHYSICAL = -5    /* density or pressure <= 0 was seen (Euler)        */
+  HWENO_ENONPHYSICAL = -5,   /* density or pressure <= 0 was seen (Euler)        */
+  HWENO_ESCRATCH = -6        /* too large for hweno_step_noalloc's scratch       */
 } hweno_status;
 
 typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_system;
@@ -223,6 +224,31 @@ hweno_status hweno_steps(const hweno_problem* prob, void* u, void* v, void* w, i
                          int32_t dt_rule, double cfl, double dt_fixed, double t_end, double* t,
                          double* dt_used, double* alpha_rec, void* ws, hipStream_t stream,
                          hipEvent_t* events);
+
+/*
+ * hweno_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same step, with the same arguments except that it takes no workspace and
+ * no stage-state buffer, and the same results bit for bit. Its workspace is
+ * a static device array of the library, 128 MiB (134217728 bytes) per GPU,
+ * held from the first call on that GPU until the process ends; nothing is
+ * allocated or freed, by the library or by any routine it calls. It runs on
+ * the current device, whose stream `stream` must be.
+ *   Limit: the step's workspace (4 KiB + 16 KiB + 2 stage states of 2 or 3
+ *   fields + the RK base derivatives; for 2D Euler 256 bytes per cell in
+ *   FP64, i.e. up to 724^2 cells, and 128 bytes per cell in FP32, up to
+ *   1023^2) must fit in the 128 MiB, else HWENO_ESCRATCH is returned before
+ *   anything is enqueued.
+ *   Sharing: every call on one GPU uses that GPU's one array, which keeps the
+ *   last call's contents (each call clears what must start at zero). Calls
+ *   that overlap in time on one GPU (different streams, or threads) race:
+ *   order them on one stream. The state flags of hweno_health are not
+ *   reported by this entry point.
+ */
+hweno_status hweno_step_noalloc(const hweno_problem* prob, void* u, void* v, void* w,
+                                int32_t dt_rule, double cfl, double dt_fixed, double t_end,
+                                double* t, double* dt_used, double* alpha_rec,
+                                hipStream_t stream);
 
 /*
  * Strip height (rows marched by one wavefront) of the 2D forward stage

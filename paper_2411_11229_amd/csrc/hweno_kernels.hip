@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <atomic>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "../../include/hweno.h"
@@ -1403,6 +1404,15 @@ __global__ __launch_bounds__(256) void source_vjp_kernel(T* __restrict__ G0, T* 
 
 }  // namespace hweno
 
+// The device scratch of hweno_step_noalloc: the workspace of a step (step
+// scalars, per-block maxima, the stage states and the RK base derivatives)
+// for callers that cannot allocate. One copy per GPU, held while the process
+// lives. Host code must not pass `scratch` itself to a kernel (in host code it
+// names a host-side stand-in): it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 // =================================================================== host side
 using namespace hweno;
 
@@ -1547,6 +1557,31 @@ size_t ghost_bytes(const hweno_problem* p, const Geometry& g) {
 }
 size_t ws_total(const hweno_problem* p, const Geometry& g) {
   return kScalarBytes + kPartialBytes + 4 * state_bytes(g) + base_bytes(g) + ghost_bytes(p, g);
+}
+
+// The part of the workspace a forward step uses (ws_layout puts it first):
+// scalars, partial maxima, X^(1), X^(2), the RK base derivatives.
+size_t ws_step_bytes(const Geometry& g) {
+  return kScalarBytes + kPartialBytes + 2 * state_bytes(g) + base_bytes(g);
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (hipGetSymbolAddress with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hweno_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HWENO_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HWENO_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HWENO_OK;
 }
 
 WsLayout ws_layout(const hweno_problem* p, void* ws, const Geometry& g) {
@@ -2053,6 +2088,7 @@ const char* hweno_status_string(hweno_status s) {
     case HWENO_EDEVICE: return "HIP runtime error";
     case HWENO_ENONFINITE: return "non-finite state";
     case HWENO_ENONPHYSICAL: return "non-physical state (density or pressure <= 0)";
+    case HWENO_ESCRATCH: return "problem exceeds the static scratch of hweno_step_noalloc";
   }
   return "unknown status";
 }
@@ -2141,6 +2177,24 @@ hweno_status hweno_steps(const hweno_problem* p, void* u, void* v, void* w, int3
                          hipEvent_t* events) {
   return run_steps(p, u, v, w, nsteps, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec,
                    nullptr, ws, stream, events);
+}
+
+hweno_status hweno_step_noalloc(const hweno_problem* p, void* u, void* v, void* w,
+                                int32_t dt_rule, double cfl, double dt_fixed, double t_end,
+                                double* t, double* dt_used, double* alpha_rec,
+                                hipStream_t stream) {
+  hweno_status st = validate(p);
+  if (st != HWENO_OK) return st;
+  if (ws_step_bytes(geometry(p)) > kScratchBytes) return HWENO_ESCRATCH;
+  if (!u || !v || !t) return HWENO_EINVAL;
+  void* ws = nullptr;
+  if ((st = scratch_on_current_device(&ws)) != HWENO_OK) return st;
+  // the scratch keeps the previous call's contents: clear the step scalars
+  // (alpha accumulators, flags) with a kernel, before the step's launches
+  ws_init_kernel<<<1, 1, 0, stream>>>((StepScalars*)ws);
+  if ((st = check_launch()) != HWENO_OK) return st;
+  return run_steps(p, u, v, w, 1, dt_rule, cfl, dt_fixed, t_end, t, dt_used, alpha_rec, nullptr,
+                   ws, stream, nullptr);
 }
 
 hweno_status hweno_set_strip_rows(int32_t rows) {

@@ -23,7 +23,8 @@ PRECISIONS = {'f64': 0, 'f32': 1}
 BASES = {'cell': 0, 'interface': 1}
 DT_RULES = {'production': 0, 'accuracy': 1, 'fixed': 2}
 STATUS = {0: 'ok', -1: 'invalid argument', -2: 'unsupported', -3: 'HIP runtime error',
-          -4: 'non-finite state', -5: 'non-physical state'}
+          -4: 'non-finite state', -5: 'non-physical state',
+          -6: 'problem exceeds the static scratch'}
 
 
 class HwenoError(RuntimeError):
@@ -64,6 +65,8 @@ _SIGS = {
                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P],
                     ctypes.c_int),
     'hweno_set_strip_rows': ([ctypes.c_int32], ctypes.c_int),
+    'hweno_step_noalloc': ([ctypes.POINTER(_CProblem), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_double, _P, _P, _P, _P], ctypes.c_int),
     'hweno_step_frozen': ([ctypes.POINTER(_CProblem)] + [_P] * 11, ctypes.c_int),
     'hweno_adjoint_step': ([ctypes.POINTER(_CProblem)] + [_P] * 14, ctypes.c_int),
     'hweno_health': ([ctypes.POINTER(_CProblem), _P, _P, ctypes.c_int32], ctypes.c_int),

@@ -191,3 +191,23 @@ def test_multi_step_and_strip_setting_validation(lib):
     assert lib.hweno_set_strip_rows(7) == 0
     assert lib.hweno_set_strip_rows(0) == 0
 
+
+def test_noalloc_step_rejects_problems_beyond_its_scratch(lib):
+    """hweno_step_noalloc checks the problem against its 128 MiB static
+    scratch before touching a device: 2D Euler FP64 at 724^2 fits (256 bytes
+    per cell), 725^2 and 1024^2 do not (HWENO_ESCRATCH); FP32 (128 bytes per
+    cell) fits at 1023^2, not at 2048^2.
+    Fake addresses, never dereferenced."""
+    a = [ctypes.c_void_p(0x1000 * (k + 1)) for k in range(6)]
+    f = lambda p: lib.hweno_step_noalloc(ctypes.byref(p), a[0], a[1], a[2], 0, 0.6, 0.0, 1.0,
+                                         a[3], None, None, None)
+    for n in (725, 1024):
+        assert f(_prob(nx=n, ny=n)) == -6
+    assert f(_prob(nx=2048, ny=2048, precision='f32')) == -6
+    # within the limit, null buffers are the first error found
+    p = _prob(nx=724, ny=724)
+    assert lib.hweno_step_noalloc(ctypes.byref(p), None, a[1], a[2], 0, 0.6, 0.0, 1.0, a[3],
+                                  None, None, None) == -1
+    p = _prob(nx=1023, ny=1023, precision='f32')
+    assert lib.hweno_step_noalloc(ctypes.byref(p), a[0], a[1], a[2], 0, 0.6, 0.0, 1.0, None,
+                                  None, None, None) == -1
