@@ -486,6 +486,22 @@ __device__ __forceinline__ void finish_row(const StageArgs<T>& A, int r, bool xw
 // its own instantiation, so the common one carries no code of the others.
 constexpr int kVarWalls = 1, kVarIface = 2, kVarSource = 4;
 
+// Tile of a 2D marcher workgroup. Workgroups go to the eight XCDs (each with
+// its own L2) in turn by linear id; this gives every XCD one contiguous run
+// of tiles in strip-major order, so that horizontally adjacent tiles, which
+// re-read each other's halo columns and share the cache lines at their
+// edges, mostly sit behind the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void marcher_tile(int& bx, int& by) {
+  const int nbx = gridDim.x, n = nbx * gridDim.y;
+  const int h = blockIdx.x + nbx * blockIdx.y;
+  const int q = n / kXcds, rem = n % kXcds;   // XCDs below rem take q + 1 tiles
+  const int x = h % kXcds;
+  const int L = x * q + min(x, rem) + h / kXcds;
+  by = L / nbx;
+  bx = L - by * nbx;
+}
+
 template <class Sys, typename T, int MODE, int VAR>
 __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   constexpr bool WALLS = (VAR & kVarWalls) != 0;
@@ -495,16 +511,18 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   const Scheme& s = A.s;
   const int lane = threadIdx.x;
   double dt, tstage;
-  if (!stage_begin<MODE>(A, blockIdx.x == 0 && blockIdx.y == 0 && lane == 0, dt, tstage)) return;
-  const int col = blockIdx.x * kXOut - kHalo + lane;
+  int bx, by;
+  marcher_tile(bx, by);
+  if (!stage_begin<MODE>(A, bx == 0 && by == 0 && lane == 0, dt, tstage)) return;
+  const int col = bx * kXOut - kHalo + lane;
   const int gcol = map_index(col, A.nx, A.bc[0], A.bc[1]);
   const bool out_col = lane >= kHalo && lane < kWave - kHalo && col < A.nx;
   const bool xm = mirrored(col, A.nx, A.bc[0], A.bc[1]);
   const int xf = fixed_side(col, A.nx, A.bc[0], A.bc[1]);
-  const int col0 = blockIdx.x * kXOut - kHalo;   // the wavefront's first column
+  const int col0 = bx * kXOut - kHalo;   // the wavefront's first column
   auto special = [](int b) { return b == kBcReflective || b == kBcDirichlet; };
   const bool xwall = (special(A.bc[0]) && col0 < 0) || (special(A.bc[1]) && col0 + kWave > A.nx);
-  const int y0 = blockIdx.y * A.rows;
+  const int y0 = by * A.rows;
   const int y1 = min(y0 + A.rows, A.ny);
   const double ax = A.alpha[0], ay = A.alpha[1];
   const T a_y = T(ay);

@@ -172,7 +172,7 @@ def _oracle_grad(w, steps, target, **kw):
     Ue, _, _ = O.run_fixed(p, U, V, W, log.dts, log.alphas)
     J = 0.5 * ((Ue - torch.tensor(target)) ** 2).sum() * p.dx * (p.dy if p.dim == 2 else 1.0)
     J.backward()
-    return [x.grad.numpy() for x in (U, V, W) if x is not None], float(J)
+    return [x.grad.numpy() for x in (U, V, W) if x is not None], float(J.detach())
 
 
 def _gpu_grad(w, steps, target, precision='f64', every=4, **kw):
