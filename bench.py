@@ -118,9 +118,10 @@ def time_forward(n, precision, steps, warmup, seed=4000, basis='cell'):
 def time_adjoint(precision, n=512, steps=200, every=20, basis='cell'):
     """Adjoint workload: 2D Euler n x n periodic smooth data (seed 5000),
     `steps` SSP-RK3 steps at the production dt of t = 0, checkpoints every
-    `every` steps; J = dx dy/2 sum (U_T - U*)^2 with U* the seed-5001 field.
-    Returns forward and backward (segment recompute + adjoint steps) wall
-    times of HwenoRollout, with the given characteristic basis."""
+    `every` steps (None: segments sized from device memory, here one segment,
+    nothing recomputed); J = dx dy/2 sum (U_T - U*)^2 with U* the seed-5001
+    field. Returns forward and backward (segment recompute + adjoint steps)
+    wall times of HwenoRollout, with the given characteristic basis."""
     import torch
     from paper_2411_11229_amd import hweno, rollout, workloads
     w = workloads.euler2d_smooth(n, seed=5000)
@@ -148,9 +149,12 @@ def time_adjoint(precision, n=512, steps=200, every=20, basis='cell'):
         ok = all(bool(torch.isfinite(x.grad).all()) for x in X)
         return t1 - t0, t2 - t1, ok
 
-    once(every)                       # warm-up
+    seg = every if every is not None else rollout.segment_length(s, steps)
+    once(min(seg, steps))             # warm-up
     fwd, bwd, ok = once(steps)
-    return dict(forward_s=fwd, backward_s=bwd, ratio=bwd / fwd, grads_finite=ok)
+    kept = rollout.state_bytes_per_step(s) * (min(seg, steps) + 1)
+    return dict(forward_s=fwd, backward_s=bwd, ratio=bwd / fwd, grads_finite=ok,
+                segment_steps=seg, kept_state_gb=kept / 1e9)
 
 
 def host_cpu():
@@ -426,6 +430,8 @@ def main():
                     help='precision of the headline run (and of --adjoint-only)')
     ap.add_argument('--basis', choices=['cell', 'interface'], default='cell',
                     help='characteristic basis of --adjoint-only')
+    ap.add_argument('--checkpoint-every', type=int, default=20,
+                    help='checkpoint segment of --adjoint-only (0: sized from device memory)')
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -441,8 +447,9 @@ def main():
         print('bench.py: no HIP device visible', file=sys.stderr)
         sys.exit(1)
     if args.adjoint_only:
+        every = None if args.checkpoint_every == 0 else args.checkpoint_every
         print(json.dumps({f'adjoint_{args.precision}_{args.basis}':
-                          time_adjoint(args.precision, basis=args.basis)}))
+                          time_adjoint(args.precision, basis=args.basis, every=every)}))
         return
     if args.basis_robustness:
         print(json.dumps({'basis_robustness': basis_robustness()}))
@@ -476,6 +483,20 @@ def main():
         if a32:
             adjoint.update(forward_s_f32=a32['forward_s'], backward_s_f32=a32['backward_s'],
                            ratio_f32=a32['ratio'])
+        # the interface (Roe) basis, and both bases with every step kept in
+        # HBM (segments sized from device memory: no recomputation)
+        ai = time_adjoint('f64', basis='interface')
+        adjoint['ratio_f64_interface'] = ai['ratio']
+        kept = {}
+        for prec, basis in (('f64', 'cell'), ('f64', 'interface'), ('f32', 'cell'),
+                            ('f32', 'interface')):
+            if prec == 'f32' and args.no_fp32:
+                continue
+            a = time_adjoint(prec, basis=basis, every=None)
+            kept[f'ratio_{prec}_{basis}'] = a['ratio']
+            kept[f'kept_state_gb_{prec}'] = a['kept_state_gb']
+            kept[f'segment_steps_{prec}'] = a['segment_steps']
+        adjoint['all_steps_kept'] = kept
     cpu = None if args.no_cpu else cpu_baseline()
     copy = copy_bandwidth()
 

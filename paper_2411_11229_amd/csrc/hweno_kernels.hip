@@ -486,13 +486,13 @@ __device__ __forceinline__ void finish_row(const StageArgs<T>& A, int r, bool xw
 // its own instantiation, so the common one carries no code of the others.
 constexpr int kVarWalls = 1, kVarIface = 2, kVarSource = 4;
 
-// Tile of a 2D marcher workgroup. Workgroups go to the eight XCDs (each with
-// its own L2) in turn by linear id; this gives every XCD one contiguous run
-// of tiles in strip-major order, so that horizontally adjacent tiles, which
-// re-read each other's halo columns and share the cache lines at their
-// edges, mostly sit behind the same L2.
+// Tile of a workgroup in a 2D grid of tiles (row-major, gridDim.x tiles a
+// row). Workgroups go to the eight XCDs (each with its own L2) in turn by
+// linear id; this gives every XCD one contiguous run of tiles, so that
+// horizontally adjacent tiles, which re-read each other's halo columns and
+// share the cache lines at their edges, mostly sit behind the same L2.
 constexpr int kXcds = 8;
-__device__ __forceinline__ void marcher_tile(int& bx, int& by) {
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   const int nbx = gridDim.x, n = nbx * gridDim.y;
   const int h = blockIdx.x + nbx * blockIdx.y;
   const int q = n / kXcds, rem = n % kXcds;   // XCDs below rem take q + 1 tiles
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   const int lane = threadIdx.x;
   double dt, tstage;
   int bx, by;
-  marcher_tile(bx, by);
+  xcd_tile(bx, by);
   if (!stage_begin<MODE>(A, bx == 0 && by == 0 && lane == 0, dt, tstage)) return;
   const int col = bx * kXOut - kHalo + lane;
   const int gcol = map_index(col, A.nx, A.bc[0], A.bc[1]);
@@ -897,8 +897,9 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
   constexpr int NC = Sys::NC;
   using Bar = typename BarOf<Sys, T>::type;
   const int lane = threadIdx.x;
-  const int row = blockIdx.y;
-  const int v = blockIdx.x * kXOut - 4 + lane;
+  int bx, row;
+  xcd_tile(bx, row);
+  const int v = bx * kXOut - 4 + lane;
   const int g = map_index(v, A.n, A.bc_lo, A.bc_hi);
   const bool interior = v >= 0 && v < A.n;
   const bool out = lane >= kHalo && lane < kWave - kHalo && v >= -2 && v < A.n + 2;
@@ -919,14 +920,14 @@ __global__ __launch_bounds__(64) void vjp_row_kernel(VjpArgs<T> A, Sys sy) {
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int f = 0; f < NF; ++f)
-        row_to_lds(A.G[f], (unsigned)(c * A.plane + base), blockIdx.x * kXOut - 4, A.n, &gin[f][c][0], lane);
+        row_to_lds(A.G[f], (unsigned)(c * A.plane + base), bx * kXOut - 4, A.n, &gin[f][c][0], lane);
     if (hj >= 0) {
 #pragma unroll
       for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
           row_to_lds(A.yhalo, (unsigned)(((hj * 4 + hside * 2 + hf) * NC + c) * A.n),
-                     blockIdx.x * kXOut - 4, A.n, &yh[hf][c][0], lane);
+                     bx * kXOut - 4, A.n, &yh[hf][c][0], lane);
     }
   }
   T U[NC], Av[NC], Ov[NC];

@@ -12,10 +12,35 @@ default, its stage states X^(1), X^(2), so the adjoint of a step needs no
 forward recomputation. The last segment, which the backward needs first, is
 kept by the forward itself (step-start and stage states, written by the
 steps it takes anyway), so only the earlier segments are recomputed.
+
+``checkpoint_every=None`` sizes the segments from device memory: the whole
+rollout is one segment (nothing recomputed) when its step-start and stage
+states fit in half of the free device memory, else the longest segment that
+does. A 512^2 FP64 Euler rollout of 200 steps keeps 15 GB that way.
 """
 import torch
 
 from . import hweno
+
+
+def state_bytes_per_step(solver, store_stages=True):
+    """Device bytes one kept step costs: its step-start state (u, v[, w])
+    and, with store_stages, its two stage states."""
+    nf = 3 if solver.prob.dim == 2 else 2
+    plane = solver.prob.ncomp * solver.prob.nx * solver.prob.ny
+    item = torch.empty((), dtype=solver.prob.dtype).element_size()
+    return nf * plane * item * (3 if store_stages else 1)
+
+
+def segment_length(solver, steps, store_stages=True, budget_bytes=None):
+    """Steps per checkpoint segment for a rollout of `steps` steps: all of
+    them when the kept states fit in budget_bytes (default: half of the free
+    device memory), else the longest segment that fits (at least 1)."""
+    if budget_bytes is None:
+        free, _ = torch.cuda.mem_get_info(solver.device)
+        budget_bytes = free // 2
+    per = state_bytes_per_step(solver, store_stages)
+    return max(1, min(steps, budget_bytes // per - 1))
 
 
 class HwenoRollout(torch.autograd.Function):
@@ -25,6 +50,8 @@ class HwenoRollout(torch.autograd.Function):
                 checkpoint_every=20, store_stages=True):
         two = solver.prob.dim == 2
         dev = solver.device
+        if checkpoint_every is None:
+            checkpoint_every = segment_length(solver, steps, store_stages)
         U = U0.detach().clone().contiguous()
         V = V0.detach().clone().contiguous()
         W = W0.detach().clone().contiguous() if two else None

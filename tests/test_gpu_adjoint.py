@@ -353,3 +353,26 @@ def test_full_size_rollout_gradient_finite_differences(basis):
           f'(FP64 response to one FP32 ulp {d32:.3e}, to one FP64 ulp {d64:.3e}; bound {bound:.3e})',
           flush=True)
     assert worst32 <= bound, (worst32, bound)
+
+
+@pytest.mark.parametrize("basis", ['cell', 'interface'])
+def test_rollout_segment_length_leaves_gradient_bit_identical(basis):
+    """The gradient does not depend on the checkpoint segments: segments of
+    7 steps (recomputed from checkpoints), one segment of all 30 steps (kept
+    by the forward) and the memory-sized default (checkpoint_every=None)
+    give the same bits, as the recomputation repeats the forward's stage
+    arithmetic with its recorded time steps and alphas."""
+    w = WL.euler2d_smooth(96, seed=5010, ny=80)
+    rng = np.random.default_rng(12)
+    target = dev(w.U + 0.05 * rng.standard_normal(w.U.shape))
+    s = solver(w, basis=basis)
+    grads = []
+    for every in (7, 30, None):
+        X = [x.requires_grad_(True) for x in state(w)]
+        o = R().rollout(s, X[0], X[1], X[2], steps=30, checkpoint_every=every)
+        (0.5 * ((o[0] - target) ** 2).sum() * w.dx * w.dy).backward()
+        grads.append([x.grad.detach() for x in X])
+    assert R().segment_length(s, 30) == 30
+    for g in grads[1:]:
+        for a, b in zip(grads[0], g):
+            assert torch.equal(a, b)
