@@ -236,9 +236,10 @@ def copy_bandwidth(gib=1.0, reps=20):
                 kind=f'device copy of {gib:g} GiB (read + write), mean of {reps}')
 
 
-def traffic_record():
-    """HBM bytes per stage launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel sources."""
+def traffic_record(precision='f64'):
+    """HBM bytes per stage launch (FP64 or FP32 stage kernel) from the
+    committed rocprofv3 counter runs, if they were taken on the current
+    kernel sources."""
     if not os.path.exists(PROFILE_JSON):
         return None
     try:
@@ -247,6 +248,8 @@ def traffic_record():
         return None
     if rec.get('kernel_source_sha256') != kernel_hash():
         return None
+    if precision == 'f32':
+        rec = rec.get('f32', {})
     return rec.get('traffic_bytes_per_launch')
 
 
@@ -470,7 +473,9 @@ def main():
         r = time_forward(args.n, 'f32', args.steps, args.warmup)
         fp32 = dict(value=r['value'], ms_per_step=r['ms_per_step'],
                     avg_stage_kernel_ms=r['avg_stage_ms'], achieved_gbs=r['achieved_gbs'],
-                    frac=r['achieved_gbs'] / HBM_PEAK_GBS)
+                    frac=r['achieved_gbs'] / HBM_PEAK_GBS,
+                    algorithmic_bytes_per_launch=r['bytes_per_launch'],
+                    traffic=traffic_record('f32'))
     adjoint = None
     if not args.no_adjoint:
         a64 = time_adjoint('f64')
@@ -500,7 +505,7 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline()
     copy = copy_bandwidth()
 
-    traffic = traffic_record()
+    traffic = traffic_record(args.precision)
     roof = dict(bound='hbm', achieved=main_run['achieved_gbs'], peak=HBM_PEAK_GBS, unit='GB/s',
                 frac=main_run['achieved_gbs'] / HBM_PEAK_GBS,
                 traffic=traffic,
