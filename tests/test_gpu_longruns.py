@@ -1,5 +1,5 @@
-"""Long 2D Euler runs on the GPU against the FP64 oracle's full runs
-(2Dfully-hweno, production time step from the stage-1 alphas each step).
+"""Long Euler runs (2D and 1D) on the GPU against the FP64 oracle's full runs
+((fully-hweno), (2Dfully-hweno), production time step from the stage-1 alphas each step).
 
 Expected values: ``tests/golden/long_runs.npz``, written by
 ``tests/golden/make_long_runs.py`` from the oracle alone (its final fields,
@@ -8,7 +8,10 @@ one-FP32-ulp perturbations of every input value).
 
 * quadrants_128: the four-quadrant Riemann data (seed 4000, 128^2,
   transmissive) to T = 0.25;
-* smooth_256: the smooth periodic data (seed 3000, 256^2), 100 steps.
+* smooth_256: the smooth periodic data (seed 3000, 256^2), 100 steps;
+* the eight seeded 1D Euler Riemann + sine runs (N = 2000, seeds
+  2000-2007) to their end times (``tests/golden/euler1d_runs.npz``, written
+  by ``tests/golden/make_euler1d_runs.py`` the same way).
 
 Bounds. FP64: the nonlinear weights amplify round-off (the oracle differs
 from itself by far more than 1e-12 after these runs when its inputs move by
@@ -101,6 +104,77 @@ def test_long_run_f32_error_against_oracle(name, gold):
         e = rel(g, gold[f'{name}_{key}'])
         linear = f32div[k] >= 2.0 ** 20 * div[k]
         bound = stages * f32div[k] if linear else 10.0 * f32div[k]
+        print(f'  {key}: FP32 rel err vs FP64 oracle {e:.3e}  (oracle FP32-ulp divergence '
+              f'{f32div[k]:.3e}, bound {bound:.3e})', flush=True)
+        assert e <= bound, f'{name} {key}: FP32 rel err {e:.3e} > {bound:.3e}'
+
+
+# ---------------------------------------------------------------- 1D Euler
+GOLD1 = os.path.join(os.path.dirname(__file__), 'golden', 'euler1d_runs.npz')
+SEEDS1 = list(range(2000, 2008))
+
+
+@pytest.fixture(scope='module')
+def gold1():
+    return np.load(GOLD1)
+
+
+def run_gpu_1d(seed, precision):
+    h = H()
+    w = WL.euler1d_riemann_sine(2000, seed=seed)
+    dtype = torch.float64 if precision == 'f64' else torch.float32
+    s = h.Solver(h.Problem(**w.problem_kwargs(), precision=precision))
+    d = lambda a: torch.tensor(a, dtype=dtype, device='cuda')
+    U, V = d(w.U), d(w.V)
+    steps, t, dts = s.run(U, V, None, t_end=w.t_end)
+    s.health()
+    host = lambda x: x.double().cpu().numpy()
+    return steps, t, host(dts), (host(U), host(V))
+
+
+@pytest.mark.parametrize("seed", SEEDS1)
+def test_euler1d_riemann_run_f64_matches_oracle(seed, gold1):
+    """All eight seeded 1D Euler Riemann + sine runs (N = 2000, transmissive,
+    production dt) to their end times, against the oracle's full runs
+    (``tests/golden/euler1d_runs.npz``, written by make_euler1d_runs.py):
+    same step count, time steps and end time, fields within 10x the oracle's
+    one-ulp divergence. Several of these runs are chaotic at the round-off
+    level (shocks steepen, the nonlinear weights switch): the divergence
+    reaches 5e-3 in u and 0.19 in v for seed 2003."""
+    print(f'seed {seed} f64', flush=True)
+    name = f'seed{seed}'
+    steps, t, dts, fields = run_gpu_1d(seed, 'f64')
+    div = gold1[f'{name}_ulp_divergence']
+    assert steps == int(gold1[f'{name}_steps'])
+    assert t == pytest.approx(float(gold1[f'{name}_t']), rel=max(10 * div[0], 1e-14))
+    # the step times, not the steps: the last step is clipped to T and takes
+    # up what the earlier steps' differences add up to
+    np.testing.assert_allclose(np.cumsum(dts), np.cumsum(gold1[f'{name}_dts']),
+                               rtol=max(10 * div[0], 1e-12))
+    for k, (g, key) in enumerate(zip(fields, 'UV')):
+        e = rel(g, gold1[f'{name}_{key}'])
+        bound = max(10.0 * div[k], 1e-12)
+        print(f'  {key}: rel err {e:.3e}  oracle one-ulp divergence {div[k]:.3e}', flush=True)
+        assert e <= bound, f'{name} {key}: rel err {e:.3e} > {bound:.3e}'
+
+
+@pytest.mark.parametrize("seed", SEEDS1)
+def test_euler1d_riemann_run_f32_error_against_oracle(seed, gold1):
+    """The same eight runs in FP32 against the FP64 oracle, with the bound
+    rule of the 2D long runs (stages x the oracle's FP32-ulp divergence where
+    its response is linear, 10x it where saturated)."""
+    print(f'seed {seed} f32', flush=True)
+    name = f'seed{seed}'
+    steps, t, dts, fields = run_gpu_1d(seed, 'f32')
+    n64 = int(gold1[f'{name}_steps'])
+    assert abs(steps - n64) <= max(1, n64 // 100)
+    assert t == pytest.approx(float(gold1[f'{name}_t']), rel=1e-3)
+    f32div = gold1[f'{name}_f32ulp_divergence']
+    div = gold1[f'{name}_ulp_divergence']
+    for k, (g, key) in enumerate(zip(fields, 'UV')):
+        e = rel(g, gold1[f'{name}_{key}'])
+        linear = f32div[k] >= 2.0 ** 20 * div[k]
+        bound = 3 * n64 * f32div[k] if linear else 10.0 * f32div[k]
         print(f'  {key}: FP32 rel err vs FP64 oracle {e:.3e}  (oracle FP32-ulp divergence '
               f'{f32div[k]:.3e}, bound {bound:.3e})', flush=True)
         assert e <= bound, f'{name} {key}: FP32 rel err {e:.3e} > {bound:.3e}'

@@ -135,6 +135,22 @@ def test_rayleigh_taylor_run_matches_oracle_and_stays_symmetric():
     s.health()
 
 
+def test_rayleigh_taylor_short_run_mirror_symmetric_to_roundoff():
+    """The oracle's own symmetry pin on the GPU: Example 4.11's data at 16x64
+    over 8 steps stay mirror-symmetric about x = 1/8 within 1e-12 of each
+    field's max (before the instability has amplified the round-off)."""
+    w = WL.rayleigh_taylor(16)
+    s = solver(w)
+    U, V, W = dev(w.U), dev(w.V), dev(w.W)
+    s.run(U, V, W, t_end=1e9, max_steps=8)
+    sign = torch.tensor([1.0, -1.0, 1.0, 1.0], dtype=torch.float64, device='cuda')[:, None, None]
+    for k, (X, sg) in enumerate(((U, sign), (V, -sign), (W, sign))):
+        asym = float((X - sg * X.flip(-1)).abs().max() / X.abs().max())
+        print(f'  field {k}: mirror asymmetry {asym:.2e}')
+        assert asym <= 1e-12
+    s.health()
+
+
 ADJ = [('rt-12x48', lambda: WL.rayleigh_taylor(12)),
        ('quadrants-dirichlet', lambda: dirichlet(WL.euler2d_quadrants(70, seed=4502, ny=40),
                                                  ('dirichlet', 'transmissive', 'reflective', 'dirichlet'),
