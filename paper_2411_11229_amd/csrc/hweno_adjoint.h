@@ -722,32 +722,30 @@ HWENO_HD void hweno_cell_iface_vjp(const Sys& sy, const Scheme& s, double h, dou
       }
       const auto q = sy.prim(U0);
       const auto e = roe ? sy.roe_eig(UL, UR) : sy.eig(q);
-      T wm[NC], w0[NC], wp[NC], am[NC], ap[NC], c[NC];
+      T wm[NC], w0[NC], wp[NC], am[NC], ap[NC];
       sy.template project<D>(e, Um, wm);
       sy.template project<D>(e, U0, w0);
       sy.template project<D>(e, Up, wp);
       sy.template project<D>(e, Am, am);
       sy.template project<D>(e, Ap, ap);
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        T r_, l_, t_;
-        hweno_point<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, r_, l_, t_);
-        c[j] = which == 0 ? r_ : (which == 1 ? l_ : t_);
-      }
+      // cotangents of the characteristic values first (R^T g needs no
+      // forward values), then each component's reverse, which also returns
+      // its forward values for the basis cotangent
       EigBar<T> eb;
       T gc[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) gc[j] = T(0);
-      unproject_vjp<D>(sy, e, c, gout, eb, gc);
+      unproject_t<D>(sy, e, gout, gc);
       T gwm[NC], gw0[NC], gwp[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         gwm[j] = T(0); gw0[j] = T(0); gwp[j] = T(0);
-        T gam = T(0), gap = T(0);
+        T gam = T(0), gap = T(0), r_, l_, t_;
         const double g = (double)gc[j];
-        hweno_point_vjp<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, which == 0 ? g : 0.0,
-                           which == 1 ? g : 0.0, which == 2 ? g : 0.0, gwm[j], gw0[j], gwp[j],
-                           gam, gap);
+        hweno_point_vjp_fused<T>(wm[j], w0[j], wp[j], am[j], ap[j], s, h, ih, which == 0 ? g : 0.0,
+                                 which == 1 ? g : 0.0, which == 2 ? g : 0.0, gwm[j], gw0[j],
+                                 gwp[j], gam, gap, r_, l_, t_);
+        unproject_eb<D>(sy, e, j, which == 0 ? r_ : (which == 1 ? l_ : t_), gout, eb);
         am[j] = gam;   // the projected derivatives are not needed again
         ap[j] = gap;
       }
