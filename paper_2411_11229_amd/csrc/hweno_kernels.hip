@@ -1284,8 +1284,10 @@ __global__ __launch_bounds__(64) void vjp_y_kernel(VjpYArgs<T> A, Sys sy) {
         tm[c] = T(0); tc[c] = T(0); tWm[c] = T(0);
         face_derivs_vjp(gwT[c], gwB[c], ih, tm[c], tc[c], accUc[c], tWm[c], accWc[c]);
       }
-      hweno_cell_vjp_b<1, IFACE>(sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, guT, guB, aW1, tm, tc,
-                                 accUc, tWm, accWc);
+      // the fused point reverse (one forward evaluation fewer) pays in FP32;
+      // in FP64 its live intermediates spill (backward 76 -> 97 ms at 512^2)
+      hweno_cell_vjp_b<1, IFACE, std::is_same<T, float>::value>(
+          sy, s, s.dy, s.idy, Ua, Ub, Uc, Wa, Wc, guT, guB, aW1, tm, tc, accUc, tWm, accWc);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         accUa[c] += tm[c];
