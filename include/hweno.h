@@ -22,9 +22,10 @@
  *   - The caller owns every buffer, including the workspace ws, whose size
  *     comes from hweno_workspace_bytes and which must be passed through
  *     hweno_workspace_init once before first use. The library allocates no
- *     device memory and keeps no device state; its only global state is
- *     host-side: a cache of occupancy queries and the strip-height setting of
- *     hweno_set_strip_rows. Calls on different streams
+ *     device memory and keeps no device state, except the static scratch
+ *     array of hweno_step_noalloc (for callers that cannot allocate); its
+ *     other global state is host-side: a cache of occupancy queries and the
+ *     strip-height setting of hweno_set_strip_rows. Calls on different streams
  *     with different workspaces are independent; calls sharing a workspace
  *     must be ordered on one stream.
  *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
@@ -72,8 +73,9 @@ typedef enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_s
  *                 variables), the derivatives v, w are 0 there;
  *   split         (y sides of 2D Euler only) a rule that changes along x and
  *                 in time, as on the bottom and top of Example 4.7: see
- *                 hweno_split. Only hweno_rhs (at t = 0) and hweno_step
- *                 accept it; hweno_step_frozen and hweno_adjoint_step return
+ *                 hweno_split. Only hweno_rhs (at t = 0) and the time
+ *                 steps (hweno_step, hweno_steps, hweno_step_noalloc) accept
+ *                 it; hweno_step_frozen and hweno_adjoint_step return
  *                 HWENO_EUNSUPPORTED.
  * The two ends of an axis are independent except for periodic. */
 typedef enum {
