@@ -3,14 +3,16 @@
 // Forward stage kernel ("marcher"): one wavefront per block. The 64 lanes
 // hold 64 consecutive cells of a row (60 output columns plus a 2-cell halo
 // on each side); x-neighbours are read across lanes. The wavefront marches
-// up a strip of rows, keeping in registers the rows the y-stencil still
-// needs, so every cell's HWENO interpolation is done once per direction and
+// up a strip of rows, keeping in registers (and, for the pointwise y-fluxes
+// and pending updates, in LDS) what the y-stencil still needs, in a tile
+// order that keeps neighbouring tiles behind one XCD's L2, so every cell's
+// HWENO interpolation is done once per direction and
 // every input value is read from memory once per strip (plus halos).
 // Per output cell and stage it does: the x-sweep (HWENO, pointwise fluxes,
 // central correction, LF flux, mixed flux, flux difference), the y-sweep
 // likewise, the residual (odeH)/(ode2H) and the SSP-RK3 combination
-// (fully-hweno)/(2Dfully-hweno), and, for stages 1-2, the max wave speed of
-// the new state for the next stage's Lax-Friedrichs alpha.
+// (fully-hweno)/(2Dfully-hweno), and the max wave speed of the new state for
+// the next stage's Lax-Friedrichs alpha (after stage 3: the next step's).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,7 +52,7 @@ struct StepScalars {
   unsigned flags;
 };
 
-// Time-step control of a stage-1 launch that computes dt itself (a2): from
+// Time-step control of a stage-1 launch that computes dt itself (flux-LF): from
 // its alphas by `rule` (production cfl / (ax/hx + ay/hy) with hx, hy = dx, dy;
 // accuracy the same with dx^(5/3), dy^(5/3); fixed dt_fixed), clipped so that
 // t + dt does not pass t_end. sc null: dt is given (frozen steps, adjoint).
@@ -746,7 +748,7 @@ __global__ __launch_bounds__(64) void stage2d_kernel(StageArgs<T> A, Sys sy) {
   }
 }
 
-// ------------------------------------------------- wave-speed reduction (a2)
+// -------------------------------------------- wave-speed reduction (flux-LF)
 // Per-block maxima of the spectral radius over interior cells, in x and y;
 // also raises the state flags.
 template <class Sys, typename T, int DIM>
@@ -808,7 +810,7 @@ __global__ __launch_bounds__(256) void alpha_out_kernel(const double* partial, i
   if (threadIdx.x == 0) { alpha[0] = ax; alpha[1] = ay; }
 }
 
-// Seeds a run of steps (a2): reduces the per-block maxima of the state's
+// Seeds a run of steps (flux-LF): reduces the per-block maxima of the state's
 // spectral radii into the next-step accumulators (the stage-1 alphas of the
 // first step) and clears the stage-2 and stage-3 accumulators.
 __global__ __launch_bounds__(256) void alpha_seed_kernel(const double* partial, int n,
@@ -1998,9 +2000,9 @@ hweno_status launch_vjp(const hweno_problem* p, const Sys& sy, const Geometry& g
   return HWENO_OK;
 }
 
-// Time-stepping loop of hweno_step(s) (a2, a10): one seeding pass (per-block
-// maxima of the spectral radii of the initial state, reduced into the
-// stage-1 alphas), then three stage launches per step. Stage 1 computes the
+// Time-stepping loop of hweno_step(s) ((fully-hweno), (2Dfully-hweno)): one
+// seeding pass (per-block maxima of the spectral radii of the initial state,
+// reduced into the stage-1 alphas), then three stage launches per step. Stage 1 computes the
 // step's dt from its alphas, stage 3 reduces the next step's stage-1 alphas
 // in its epilogue, so steady-state steps launch the three stage kernels only.
 hweno_status run_steps(const hweno_problem* p, void* u, void* v, void* w, int32_t nsteps,

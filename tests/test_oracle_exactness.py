@@ -32,7 +32,7 @@ def _quartic_samples(dx, n=6):
 
 
 def test_hermite_exactness_with_linear_weights():
-    """P1: with eps so large that tau/(beta+eps) vanishes, omega = linear
+    """Hermite exactness: with eps so large that tau/(beta+eps) vanishes, omega = linear
     weights and the gamma-combination collapses to p0, which is exact for
     quartics: u at both faces, p0' at the faces and the centre."""
     dx = 0.3
@@ -49,7 +49,7 @@ def test_hermite_exactness_with_linear_weights():
 
 
 def test_linear_data_exact_for_nonlinear_weights():
-    """P2: u = a + b x, v = b makes every candidate exact, so the result is
+    """Consistency for any weights: u = a + b x, v = b makes every candidate exact, so the result is
     exact whatever the (nonlinear, default-eps) weights are."""
     a, b = RNG.normal(size=(2, 8))
     xi = RNG.uniform(-2, 2, size=8)
@@ -80,7 +80,7 @@ def test_weights_pick_smooth_stencil_at_a_jump():
 
 @pytest.mark.parametrize("case", ["burgers1d", "euler1d", "euler2d", "burgers2d", "adv2d"])
 def test_periodic_conservation(case):
-    """P4: sum(u) of every component is invariant to round-off (telescoping
+    """Conservation: sum(u) of every component is invariant to round-off (telescoping
     flux differences of (odeH)/(ode2H) over periodic cells)."""
     if case == "burgers1d":
         w = WL.random_smooth_1d(24, 'burgers', seed=3)
@@ -105,7 +105,7 @@ def test_periodic_conservation(case):
 
 
 def test_nonlinear_weights_tend_to_linear_on_smooth_data():
-    """P5: max |omega^gamma - gamma| over the cells of u = 0.5 + sin(pi x) on
+    """Weights tend to the linear ones: max |omega^gamma - gamma| over the cells of u = 0.5 + sin(pi x) on
     [0,2] decays monotonically with N and is below 1e-3 from N = 160 on."""
     devs = []
     for n in (20, 40, 80, 160, 320, 640):
@@ -123,9 +123,9 @@ def test_nonlinear_weights_tend_to_linear_on_smooth_data():
 
 @pytest.mark.slow
 def test_fifth_order_convergence_advection():
-    """P6: linear advection of the seeded C1 data to T = 2 (exact = u0) with
-    the accuracy time step, N = 20 ... 320; every L-infinity order from
-    N = 40 on is >= 4.5."""
+    """Fifth order: linear advection of the seeded data 0.5 + sin(pi x) + four
+    1e-3 modes to T = 2 (exact = u0) with the accuracy time step,
+    N = 20 ... 320; every L-infinity order from N = 40 on is >= 4.5."""
     errs, ns = [], (20, 40, 80, 160, 320)
     for n in ns:
         w = WL.advection1d_modes(n, seed=1000)
