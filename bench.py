@@ -185,7 +185,7 @@ def cpu_baseline(n=1024, steps=2, seed=4000):
     """The FP64 oracle (unchanged) on a bounded sample: the same four-quadrant
     generator at n x n, `steps` SSP-RK3 steps; NumPy on one thread (about
     20 s), and the same oracle source on torch-CPU float64 with the host's
-    threads (at most 16, the box's share)."""
+    threads (at most 16, the host's share of one GPU's cores)."""
     import numpy as np
     import torch
     from oracle import hweno as O
