@@ -86,10 +86,11 @@ class HipEvents:
             self.hip.hipEventDestroy(self.ev[i])
 
 
-def time_forward(n, precision, steps, warmup, seed=4000, basis='cell'):
+def time_forward(n, precision, steps, warmup, seed=4000, basis='cell', ny=None):
     import torch
     from paper_2411_11229_amd import hweno, workloads
-    w = workloads.euler2d_quadrants(n, seed=seed)
+    ny = n if ny is None else ny
+    w = workloads.euler2d_quadrants(n, seed=seed, ny=ny)
     prob = hweno.Problem(**w.problem_kwargs(), precision=precision, basis=basis)
     s = hweno.Solver(prob)
     dt_ = prob.dtype
@@ -110,7 +111,7 @@ def time_forward(n, precision, steps, warmup, seed=4000, basis='cell'):
     ev.close()
     s.health()
     sim_t = float(t.item())
-    cells = n * n
+    cells = n * ny
     flat = [x for row in stage_ms for x in row]
     avg_stage = sum(flat) / len(flat)
     esize = 8 if precision == 'f64' else 4
@@ -416,6 +417,19 @@ def double_mach_time(nx=1600):
                 rho_max=float(U[0].max()), rho_min=float(U[0].min()))
 
 
+def share_times(n, g, steps, warmup):
+    """Stage kernels on the per-GPU shape of a g-way y-slab decomposition of
+    the n x n four-quadrant workload (n x n/g cells, transmissive y sides
+    standing in for the halo rows a neighbour would send), FP64 and FP32,
+    against the full n x n grid."""
+    out = dict(shape=f'{n}x{n // g}', slabs=g)
+    for prec in ('f64', 'f32'):
+        r = time_forward(n, prec, steps, warmup, ny=n // g)
+        out[prec] = dict(value=r['value'], avg_stage_ms=r['avg_stage_ms'],
+                         frac=r['achieved_gbs'] / HBM_PEAK_GBS, ms_per_step=r['ms_per_step'])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument('--gpus', type=int, default=1)
@@ -436,6 +450,9 @@ def main():
                     help='eager vs HIP-graph stepping on launch-bound sizes (1D Euler, Example 4.11)')
     ap.add_argument('--rayleigh-taylor', action='store_true',
                     help='time the Rayleigh-Taylor example at the paper\'s meshes instead')
+    ap.add_argument('--share', type=int, metavar='G',
+                    help='time the stage kernels on one of G y-slabs of the n x n grid instead '
+                         '(the per-GPU shape of a G-way domain decomposition)')
     ap.add_argument('--precision', choices=['f64', 'f32'], default='f64',
                     help='precision of the headline run (and of --adjoint-only)')
     ap.add_argument('--basis', choices=['cell', 'interface'], default='cell',
@@ -472,6 +489,9 @@ def main():
         return
     if args.launch_bound:
         print(json.dumps({'launch_bound': launch_bound_times()}))
+        return
+    if args.share:
+        print(json.dumps({'share': share_times(args.n, args.share, args.steps, args.warmup)}))
         return
 
     main_run = time_forward(args.n, args.precision, args.steps, args.warmup)
