@@ -244,10 +244,10 @@ def copy_bandwidth(gib=1.0, reps=20):
                 kind=f'device copy of {gib:g} GiB (read + write), mean of {reps}')
 
 
-def traffic_record(precision='f64'):
-    """HBM bytes per stage launch (FP64 or FP32 stage kernel) from the
-    committed rocprofv3 counter runs, if they were taken on the current
-    kernel sources."""
+def profile_record(precision='f64'):
+    """The committed rocprofv3 counter summary of the FP64 or FP32 stage
+    kernel (HBM traffic, VALU issue), if it was taken on the current kernel
+    sources, else None."""
     if not os.path.exists(PROFILE_JSON):
         return None
     try:
@@ -256,9 +256,21 @@ def traffic_record(precision='f64'):
         return None
     if rec.get('kernel_source_sha256') != kernel_hash():
         return None
-    if precision == 'f32':
-        rec = rec.get('f32', {})
-    return rec.get('traffic_bytes_per_launch')
+    return rec.get('f32', {}) if precision == 'f32' else rec
+
+
+def traffic_record(precision='f64'):
+    """HBM bytes per stage launch from the committed counter runs, or None."""
+    rec = profile_record(precision)
+    return None if rec is None else rec.get('traffic_bytes_per_launch')
+
+
+def valu_record(precision='f64'):
+    """VALU issue of the stage kernel from the committed counter runs
+    (instructions per launch, the shares of wavefront and SIMD cycles issuing
+    VALU, and the cycles the VALU work alone needs), or None."""
+    rec = profile_record(precision)
+    return None if rec is None else rec.get('valu')
 
 
 def copy_probe(gib=1.0, reps=10):
@@ -502,7 +514,7 @@ def main():
                     avg_stage_kernel_ms=r['avg_stage_ms'], achieved_gbs=r['achieved_gbs'],
                     frac=r['achieved_gbs'] / HBM_PEAK_GBS,
                     algorithmic_bytes_per_launch=r['bytes_per_launch'],
-                    traffic=traffic_record('f32'))
+                    traffic=traffic_record('f32'), valu=valu_record('f32'))
     adjoint = None
     if not args.no_adjoint:
         a64 = time_adjoint('f64')
@@ -540,7 +552,8 @@ def main():
                 algorithmic_bytes_per_launch=main_run['bytes_per_launch'],
                 avg_launch_ms=main_run['avg_stage_ms'],
                 stage_launch_ms=main_run['stage_ms_mean'],
-                achievable_copy_gbs=copy['achieved'])
+                achievable_copy_gbs=copy['achieved'],
+                valu=valu_record(args.precision))
     out = {
         'metric': '2D Euler cell-updates/s per RK stage',
         'value': main_run['value'],
