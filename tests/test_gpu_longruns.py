@@ -11,7 +11,9 @@ one-FP32-ulp perturbations of every input value).
 * smooth_256: the smooth periodic data (seed 3000, 256^2), 100 steps;
 * the eight seeded 1D Euler Riemann + sine runs (N = 2000, seeds
   2000-2007) to their end times (``tests/golden/euler1d_runs.npz``, written
-  by ``tests/golden/make_euler1d_runs.py`` the same way).
+  by ``tests/golden/make_euler1d_runs.py`` the same way);
+* three more four-quadrant seeds at 128^2 to T = 0.25
+  (``tests/golden/quadrant_runs.npz``, ``make_quadrant_runs.py``).
 
 Bounds. FP64: the nonlinear weights amplify round-off (the oracle differs
 from itself by far more than 1e-12 after these runs when its inputs move by
@@ -173,6 +175,71 @@ def test_euler1d_riemann_run_f32_error_against_oracle(seed, gold1):
     div = gold1[f'{name}_ulp_divergence']
     for k, (g, key) in enumerate(zip(fields, 'UV')):
         e = rel(g, gold1[f'{name}_{key}'])
+        linear = f32div[k] >= 2.0 ** 20 * div[k]
+        bound = 3 * n64 * f32div[k] if linear else 10.0 * f32div[k]
+        print(f'  {key}: FP32 rel err vs FP64 oracle {e:.3e}  (oracle FP32-ulp divergence '
+              f'{f32div[k]:.3e}, bound {bound:.3e})', flush=True)
+        assert e <= bound, f'{name} {key}: FP32 rel err {e:.3e} > {bound:.3e}'
+
+
+# ------------------------------------------- more four-quadrant seeds, 2D
+GOLD3 = os.path.join(os.path.dirname(__file__), 'golden', 'quadrant_runs.npz')
+SEEDS3 = [int(x) for x in np.load(GOLD3)['seeds']] if os.path.exists(GOLD3) else []
+
+
+@pytest.fixture(scope='module')
+def gold3():
+    return np.load(GOLD3)
+
+
+def run_gpu_quadrants(seed, precision):
+    h = H()
+    w = WL.euler2d_quadrants(128, seed=seed)
+    dtype = torch.float64 if precision == 'f64' else torch.float32
+    s = h.Solver(h.Problem(**w.problem_kwargs(), precision=precision))
+    d = lambda a: torch.tensor(a, dtype=dtype, device='cuda')
+    U, V, W = d(w.U), d(w.V), d(w.W)
+    steps, t, dts = s.run(U, V, W, t_end=w.t_end)
+    s.health()
+    host = lambda x: x.double().cpu().numpy()
+    return steps, t, host(dts), (host(U), host(V), host(W))
+
+
+@pytest.mark.parametrize("seed", SEEDS3)
+def test_quadrant_seed_run_f64_matches_oracle(seed, gold3):
+    """Three more four-quadrant seeds at 128^2 to T = 0.25 against the
+    oracle's full runs (``tests/golden/quadrant_runs.npz``, written by
+    make_quadrant_runs.py): same step count and step times, fields within
+    10x the oracle's one-ulp divergence."""
+    print(f'quadrants seed {seed} f64', flush=True)
+    name = f'seed{seed}'
+    steps, t, dts, fields = run_gpu_quadrants(seed, 'f64')
+    div = gold3[f'{name}_ulp_divergence']
+    assert steps == int(gold3[f'{name}_steps'])
+    assert t == pytest.approx(float(gold3[f'{name}_t']), rel=max(10 * div[0], 1e-14))
+    np.testing.assert_allclose(np.cumsum(dts), np.cumsum(gold3[f'{name}_dts']),
+                               rtol=max(10 * div[0], 1e-12))
+    for k, (g, key) in enumerate(zip(fields, 'UVW')):
+        e = rel(g, gold3[f'{name}_{key}'])
+        bound = max(10.0 * div[k], 1e-12)
+        print(f'  {key}: rel err {e:.3e}  oracle one-ulp divergence {div[k]:.3e}', flush=True)
+        assert e <= bound, f'{name} {key}: rel err {e:.3e} > {bound:.3e}'
+
+
+@pytest.mark.parametrize("seed", SEEDS3)
+def test_quadrant_seed_run_f32_error_against_oracle(seed, gold3):
+    """The same runs in FP32 against the FP64 oracle (the bound rule of the
+    other long runs)."""
+    print(f'quadrants seed {seed} f32', flush=True)
+    name = f'seed{seed}'
+    steps, t, dts, fields = run_gpu_quadrants(seed, 'f32')
+    n64 = int(gold3[f'{name}_steps'])
+    assert abs(steps - n64) <= max(1, n64 // 100)
+    assert t == pytest.approx(float(gold3[f'{name}_t']), rel=1e-3)
+    f32div = gold3[f'{name}_f32ulp_divergence']
+    div = gold3[f'{name}_ulp_divergence']
+    for k, (g, key) in enumerate(zip(fields, 'UVW')):
+        e = rel(g, gold3[f'{name}_{key}'])
         linear = f32div[k] >= 2.0 ** 20 * div[k]
         bound = 3 * n64 * f32div[k] if linear else 10.0 * f32div[k]
         print(f'  {key}: FP32 rel err vs FP64 oracle {e:.3e}  (oracle FP32-ulp divergence '
