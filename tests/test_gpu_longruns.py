@@ -209,15 +209,23 @@ def run_gpu_quadrants(seed, precision):
 def test_quadrant_seed_run_f64_matches_oracle(seed, gold3):
     """Three more four-quadrant seeds at 128^2 to T = 0.25 against the
     oracle's full runs (``tests/golden/quadrant_runs.npz``, written by
-    make_quadrant_runs.py): same step count and step times, fields within
-    10x the oracle's one-ulp divergence."""
+    make_quadrant_runs.py): the step count (to within one step where the
+    runs' time drift allows it), step times and fields within 10x the
+    oracle's one-ulp divergence."""
     print(f'quadrants seed {seed} f64', flush=True)
     name = f'seed{seed}'
     steps, t, dts, fields = run_gpu_quadrants(seed, 'f64')
     div = gold3[f'{name}_ulp_divergence']
-    assert steps == int(gold3[f'{name}_steps'])
+    odts = gold3[f'{name}_dts']
+    # the step times may drift by up to 10x the one-ulp divergence of the
+    # end time; where that exceeds a whole step the run may take one step
+    # more or fewer than the oracle's (these runs are chaotic at the
+    # round-off level)
+    slack = 10 * div[0] * float(gold3[f'{name}_t'])
+    assert abs(steps - len(odts)) <= (1 if slack > odts.min() else 0)
     assert t == pytest.approx(float(gold3[f'{name}_t']), rel=max(10 * div[0], 1e-14))
-    np.testing.assert_allclose(np.cumsum(dts), np.cumsum(gold3[f'{name}_dts']),
+    m = min(steps, len(odts)) - 1
+    np.testing.assert_allclose(np.cumsum(dts)[:m], np.cumsum(odts)[:m],
                                rtol=max(10 * div[0], 1e-12))
     for k, (g, key) in enumerate(zip(fields, 'UVW')):
         e = rel(g, gold3[f'{name}_{key}'])
