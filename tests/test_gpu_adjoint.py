@@ -184,7 +184,7 @@ def _gpu_grad(w, steps, target, precision='f64', every=4, **kw):
     dy = w.dy if w.dim == 2 else 1.0
     J = 0.5 * ((outs[0].double() - dev(target)) ** 2).sum() * w.dx * dy
     J.backward()
-    return [host(x.grad) for x in X], float(J)
+    return [host(x.grad) for x in X], float(J.detach())
 
 
 def _perturbed(w, rel, seed=0):
