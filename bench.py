@@ -47,7 +47,9 @@ def kernel_hash():
         text = open(os.path.join(ROOT, p)).read()
         text = re.sub(r'/\*.*?\*/', ' ', text, flags=re.S)
         text = re.sub(r'//[^\n]*', ' ', text)
-        h.update(' '.join(text.split()).encode())
+        # blank space matters only between two word characters
+        text = re.sub(r'(?<=\w)\s+(?=\w)', ' ', text)
+        h.update(re.sub(r'(?<!\w)\s+|\s+(?!\w)', '', text).encode())
     return h.hexdigest()
 
 
