@@ -243,7 +243,7 @@ def test_rollout_gradient_matches_oracle(name, mk, steps):
     kw = options(name)
     go, Jo = _oracle_grad(w, steps, target, **kw)
     gg, Jg = _gpu_grad(w, steps, target, **kw)
-    assert Jg == pytest.approx(Jo, rel=1e-10)
+    assert Jg == pytest.approx(Jo, rel=1e-10, abs=0)
     for k, (a, b) in enumerate(zip(gg, go)):
         err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
         print(f'  field {k}: rel err {err:.3e}')

@@ -179,7 +179,7 @@ def test_largest_state_array_sampled():
     U0 = {c: host(U[:, j, i]) for c, (j, i) in enumerate(cells)}
     s.step(U, V, W, t, 1e9, dt_used=dt_used, stages=stages)
     dt = O.time_step(p, alpha, 'production', 0.6)
-    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-12)
+    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-12, abs=0)
     X1 = stages[:3 * 4 * n * n].view(3, 4, n, n)
     for c, ((j, i), r) in enumerate(zip(cells, ref)):
         exp = (U0[c] + dt * r[0], r[3] + dt * r[1], r[4] + dt * r[2])
@@ -255,6 +255,6 @@ def test_largest_state_array_adjoint_dot_product():
     e = 1e-7
     fd = (4 * D(e) - D(2 * e)) / 3
     print(f'  adjoint {adj:.12e}  fd {fd:.12e}')
-    assert adj == pytest.approx(fd, rel=1e-6)
+    assert adj == pytest.approx(fd, rel=1e-6, abs=0)
     del X, lam, delta, s
     torch.cuda.empty_cache()

@@ -83,7 +83,7 @@ def test_long_run_f64_matches_oracle(name, gold):
     assert steps == int(gold[f'{name}_steps'])
     # the end time is the sum of the time steps (exact where the last step
     # was clipped to T)
-    assert t == pytest.approx(float(gold[f'{name}_t']), rel=max(10 * div[0], 1e-14))
+    assert t == pytest.approx(float(gold[f'{name}_t']), rel=max(10 * div[0], 1e-14), abs=0)
     np.testing.assert_allclose(dts, gold[f'{name}_dts'], rtol=max(10 * div[0], 1e-12))
     for k, (g, key) in enumerate(zip(fields, 'UVW')):
         e = rel(g, gold[f'{name}_{key}'])
@@ -98,7 +98,7 @@ def test_long_run_f32_error_against_oracle(name, gold):
     steps, t, dts, fields = run_gpu(name, 'f32')
     n64 = int(gold[f'{name}_steps'])
     assert abs(steps - n64) <= max(1, n64 // 100)
-    assert t == pytest.approx(float(gold[f'{name}_t']), rel=1e-3)
+    assert t == pytest.approx(float(gold[f'{name}_t']), rel=1e-3, abs=0)
     f32div = gold[f'{name}_f32ulp_divergence']
     div = gold[f'{name}_ulp_divergence']
     stages = 3 * n64
@@ -148,7 +148,7 @@ def test_euler1d_riemann_run_f64_matches_oracle(seed, gold1):
     steps, t, dts, fields = run_gpu_1d(seed, 'f64')
     div = gold1[f'{name}_ulp_divergence']
     assert steps == int(gold1[f'{name}_steps'])
-    assert t == pytest.approx(float(gold1[f'{name}_t']), rel=max(10 * div[0], 1e-14))
+    assert t == pytest.approx(float(gold1[f'{name}_t']), rel=max(10 * div[0], 1e-14), abs=0)
     # the step times, not the steps: the last step is clipped to T and takes
     # up what the earlier steps' differences add up to
     np.testing.assert_allclose(np.cumsum(dts), np.cumsum(gold1[f'{name}_dts']),
@@ -170,7 +170,7 @@ def test_euler1d_riemann_run_f32_error_against_oracle(seed, gold1):
     steps, t, dts, fields = run_gpu_1d(seed, 'f32')
     n64 = int(gold1[f'{name}_steps'])
     assert abs(steps - n64) <= max(1, n64 // 100)
-    assert t == pytest.approx(float(gold1[f'{name}_t']), rel=1e-3)
+    assert t == pytest.approx(float(gold1[f'{name}_t']), rel=1e-3, abs=0)
     f32div = gold1[f'{name}_f32ulp_divergence']
     div = gold1[f'{name}_ulp_divergence']
     for k, (g, key) in enumerate(zip(fields, 'UV')):
@@ -223,7 +223,7 @@ def test_quadrant_seed_run_f64_matches_oracle(seed, gold3):
     # round-off level)
     slack = 10 * div[0] * float(gold3[f'{name}_t'])
     assert abs(steps - len(odts)) <= (1 if slack > odts.min() else 0)
-    assert t == pytest.approx(float(gold3[f'{name}_t']), rel=max(10 * div[0], 1e-14))
+    assert t == pytest.approx(float(gold3[f'{name}_t']), rel=max(10 * div[0], 1e-14), abs=0)
     m = min(steps, len(odts)) - 1
     np.testing.assert_allclose(np.cumsum(dts)[:m], np.cumsum(odts)[:m],
                                rtol=max(10 * div[0], 1e-12))
@@ -243,7 +243,7 @@ def test_quadrant_seed_run_f32_error_against_oracle(seed, gold3):
     steps, t, dts, fields = run_gpu_quadrants(seed, 'f32')
     n64 = int(gold3[f'{name}_steps'])
     assert abs(steps - n64) <= max(1, n64 // 100)
-    assert t == pytest.approx(float(gold3[f'{name}_t']), rel=1e-3)
+    assert t == pytest.approx(float(gold3[f'{name}_t']), rel=1e-3, abs=0)
     f32div = gold3[f'{name}_f32ulp_divergence']
     div = gold3[f'{name}_ulp_divergence']
     for k, (g, key) in enumerate(zip(fields, 'UVW')):

@@ -182,8 +182,8 @@ def test_step_matches_oracle_f64(name, mk, rule):
     a1 = O.max_speed(p, w.U)
     dt = O.time_step(p, a1, rule, 0.6)
     U3, V3, W3, als = O.step(p, w.U, w.V, w.W, dt)
-    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-14)
-    assert host(t)[0] == pytest.approx(dt, rel=1e-14)
+    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-14, abs=0)
+    assert host(t)[0] == pytest.approx(dt, rel=1e-14, abs=0)
     r = host(rec).reshape(3, 2)
     for k in range(3):
         np.testing.assert_allclose(r[k, :w.dim], np.array(als[k])[:w.dim], rtol=1e-12)
@@ -219,7 +219,7 @@ def test_last_step_clipped_to_end_time():
     dt_used = torch.zeros(1, dtype=torch.float64, device='cuda')
     s.step(U, V, None, t, 0.3 + 1e-5, dt_used=dt_used)
     assert float(t.item()) == 0.3 + 1e-5
-    assert float(dt_used.item()) == pytest.approx(1e-5, rel=1e-9)
+    assert float(dt_used.item()) == pytest.approx(1e-5, rel=1e-9, abs=0)
 
 
 def test_table1_burgers_run_reproduces_paper_on_gpu():
@@ -239,7 +239,7 @@ def test_table1_burgers_run_reproduces_paper_on_gpu():
     u = 0.5 + np.sin(ex)
     for _ in range(60):
         u = u - (u - 0.5 - np.sin(ex - u * 0.5)) / (1.0 + np.cos(ex - u * 0.5) * 0.5)
-    assert np.max(np.abs(host(U)[0] - u)) == pytest.approx(1.255e-5, rel=2e-3)
+    assert np.max(np.abs(host(U)[0] - u)) == pytest.approx(1.255e-5, rel=2e-3, abs=0)
 
 
 def test_periodic_conservation_on_gpu():
@@ -379,7 +379,7 @@ def test_full_size_quadrants_2048_sampled(precision):
     dt_used = torch.zeros(1, dtype=torch.float64, device='cuda')
     s.step(U, V, W, t, w.t_end, dt_used=dt_used, stages=stages)
     dt = O.time_step(p, alpha, 'production', 0.6)
-    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-12)
+    assert host(dt_used)[0] == pytest.approx(dt, rel=1e-12, abs=0)
     X1 = host(stages)[:3 * w.U.size].reshape((3,) + w.U.shape)
     for (j, i), r in zip(cells, ref):
         exp = (w.U[:, j, i] + dt * r[0], r[3] + dt * r[1], r[4] + dt * r[2])

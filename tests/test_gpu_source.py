@@ -106,7 +106,7 @@ def test_source_and_fixed_states_step_matches_oracle_f64(name, w):
     s.step(U, V, W, t, 1e9, dt_used=dt)
     alpha = O.max_speed(p, w.U)
     dto = O.time_step(p, alpha)
-    assert float(dt.item()) == pytest.approx(dto, rel=1e-14)
+    assert float(dt.item()) == pytest.approx(dto, rel=1e-14, abs=0)
     Uo, Vo, Wo, _ = O.step(p, w.U, w.V, w.W, dto, (alpha, None, None))
     for k, (g, r) in enumerate(zip((U, V, W), (Uo, Vo, Wo))):
         if r is None:
@@ -210,7 +210,7 @@ def test_adjoint_step_with_source_and_fixed_states(name, mk):
             return sum(float((l * (p_ - m)).sum()) for l, p_, m in zip(lam, Xp, Xm)) / (2 * e)
         fd = (4 * D(1e-7) - D(2e-7)) / 3
         print(f'  adjoint {adj:.12e}  fd {fd:.12e}')
-        assert adj == pytest.approx(fd, rel=1e-6)
+        assert adj == pytest.approx(fd, rel=1e-6, abs=0)
 
 
 def test_rayleigh_taylor_rollout_gradient_matches_oracle():
@@ -219,7 +219,7 @@ def test_rayleigh_taylor_rollout_gradient_matches_oracle():
     target = w.U + 0.05 * rng.standard_normal(w.U.shape)
     go, Jo = _oracle_grad(w, 4, target)
     gg, Jg = _gpu_grad(w, 4, target, every=2)
-    assert Jg == pytest.approx(Jo, rel=1e-10)
+    assert Jg == pytest.approx(Jo, rel=1e-10, abs=0)
     for k, (a, b) in enumerate(zip(gg, go)):
         err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
         print(f'  field {k}: rel err {err:.3e}')

@@ -45,12 +45,12 @@ def test_candidate_values_and_derivatives(trial):
     assert p0 == pytest.approx(deriv_at(c, 0, 0.5), rel=1e-12, abs=1e-12)
     assert dp0 == pytest.approx(deriv_at(c, 1, 0.5) / dx, rel=1e-12, abs=1e-12)
     # p1 through (x_{i-1}, x_i), p2 through (x_i, x_{i+1}), evaluated at xi = 1/2
-    assert p1 == pytest.approx(u0 + 0.5 * (u0 - um), rel=1e-14)
-    assert p2 == pytest.approx(0.5 * (u0 + up), rel=1e-14)
+    assert p1 == pytest.approx(u0 + 0.5 * (u0 - um), rel=1e-14, abs=0)
+    assert p2 == pytest.approx(0.5 * (u0 + up), rel=1e-14, abs=0)
     d0, d1, d2 = O.candidate_derivatives_at_centre(um, u0, up, vm, vp, dx)
     assert d0 == pytest.approx(deriv_at(c, 1, 0.0) / dx, rel=1e-12, abs=1e-12)
-    assert d1 == pytest.approx((u0 - um) / dx, rel=1e-14)
-    assert d2 == pytest.approx((up - u0) / dx, rel=1e-14)
+    assert d1 == pytest.approx((u0 - um) / dx, rel=1e-14, abs=0)
+    assert d2 == pytest.approx((up - u0) / dx, rel=1e-14, abs=0)
 
 
 @pytest.mark.parametrize("trial", range(5))
@@ -66,9 +66,9 @@ def test_smoothness_indicator_closed_form_equals_definition(trial):
         integ = P.polyint(sq)
         beta0 += P.polyval(0.5, integ) - P.polyval(-0.5, integ)
     b0, b1, b2 = O.smoothness_indicators(um, u0, up, vm, vp, dx)
-    assert b0 == pytest.approx(beta0, rel=1e-11)
-    assert b1 == pytest.approx((u0 - um) ** 2, rel=1e-14)
-    assert b2 == pytest.approx((up - u0) ** 2, rel=1e-14)
+    assert b0 == pytest.approx(beta0, rel=1e-11, abs=0)
+    assert b1 == pytest.approx((u0 - um) ** 2, rel=1e-14, abs=0)
+    assert b2 == pytest.approx((up - u0) ** 2, rel=1e-14, abs=0)
 
 
 def quintic_P(fm1, f0, fp1, fp2, hm1, hp2, dx):

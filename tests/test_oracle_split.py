@@ -64,10 +64,10 @@ def test_double_mach_states_satisfy_rankine_hugoniot():
     un2, un1 = u2 * n[0] + v2 * n[1], u1 * n[0] + v1 * n[1]
     ut2 = -u2 * n[1] + v2 * n[0]
     m1, m2 = r1 * (un1 - s), r2 * (un2 - s)
-    assert m2 == pytest.approx(m1, rel=1e-3)
-    assert r2 * (un2 - s) ** 2 + p2 == pytest.approx(r1 * (un1 - s) ** 2 + p1, rel=1e-3)
+    assert m2 == pytest.approx(m1, rel=1e-3, abs=0)
+    assert r2 * (un2 - s) ** 2 + p2 == pytest.approx(r1 * (un1 - s) ** 2 + p1, rel=1e-3, abs=0)
     h = lambda r, p: g / (g - 1.0) * p / r
-    assert h(r2, p2) + 0.5 * (un2 - s) ** 2 == pytest.approx(h(r1, p1) + 0.5 * (un1 - s) ** 2, rel=1e-3)
+    assert h(r2, p2) + 0.5 * (un2 - s) ** 2 == pytest.approx(h(r1, p1) + 0.5 * (un1 - s) ** 2, rel=1e-3, abs=0)
     assert abs(ut2) < 1e-12                                 # no tangential velocity jump
 
 

@@ -7,7 +7,9 @@ Time step for the accuracy tests: dt = 0.6 dx^{5/3} / (alpha_x + alpha_y),
 with alpha from the state at the start of each step and the last step clipped
 to the end time; with dt = 0.6 dx / alpha the Table-1 error at N = 640 is three
 orders of magnitude larger than printed, so this reading is fixed by the
-tables themselves. Rows at round-off level (Table 2, N = 320) are not pins.
+tables themselves. Rows at round-off level (Table 2, N = 320) are not pins;
+Table 4 at N = 80, 160 and Table 3 at N = 320 are checked on the GPU
+(test_gpu_tables.py), where they take seconds.
 """
 import json
 import math
@@ -59,30 +61,30 @@ def test_table1_burgers1d(n):
     U = _run(w, GOLD['table1_burgers1d']['gamma0'])
     e = np.abs(U[0] - burgers1d_exact(w.x, w.t_end))
     _, l1, linf = _row('table1_burgers1d', n)
-    assert e.max() == pytest.approx(linf, rel=REL)
-    assert e.mean() / (2 * math.pi) == pytest.approx(l1, rel=REL)
+    assert e.max() == pytest.approx(linf, rel=REL, abs=0)
+    assert e.mean() / (2 * math.pi) == pytest.approx(l1, rel=REL, abs=0)
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("n", [20, 40, 80])
+@pytest.mark.parametrize("n", [20, 40, 80, 160])
 def test_table2_euler1d(n):
     w = WL.paper_euler1d(n)
     U = _run(w, GOLD['table2_euler1d']['gamma0'])
     e = np.abs(U[0] - w.U[0])          # exact density at t = 2 equals the initial one
     _, l1, linf = _row('table2_euler1d', n)
-    assert e.max() == pytest.approx(linf, rel=REL)
-    assert e.mean() == pytest.approx(l1, rel=REL)
+    assert e.max() == pytest.approx(linf, rel=REL, abs=0)
+    assert e.mean() == pytest.approx(l1, rel=REL, abs=0)
 
 
-@pytest.mark.parametrize("n", [20, 40, 80])
+@pytest.mark.parametrize("n", [20, 40, 80, pytest.param(160, marks=pytest.mark.slow)])
 def test_table3_burgers2d(n):
     w = WL.paper_burgers2d(n)
     U = _run(w, GOLD['table3_burgers2d']['gamma0'])
     X, Y = np.meshgrid(w.x, w.y)
     e = np.abs(U[0] - burgers2d_exact(X, Y, w.t_end))
     _, l1, linf = _row('table3_burgers2d', n)
-    assert e.max() == pytest.approx(linf, rel=REL)
-    assert e.mean() == pytest.approx(l1, rel=REL)
+    assert e.max() == pytest.approx(linf, rel=REL, abs=0)
+    assert e.mean() == pytest.approx(l1, rel=REL, abs=0)
 
 
 @pytest.mark.slow
@@ -92,8 +94,8 @@ def test_table4_euler2d(n):
     U = _run(w, GOLD['table4_euler2d']['gamma0'])
     e = np.abs(U[0] - w.U[0])
     _, l1, linf = _row('table4_euler2d', n)
-    assert e.max() == pytest.approx(linf, rel=REL)
-    assert e.mean() == pytest.approx(l1, rel=REL)
+    assert e.max() == pytest.approx(linf, rel=REL, abs=0)
+    assert e.mean() == pytest.approx(l1, rel=REL, abs=0)
 
 
 def test_mach2000_production_time_step():
@@ -102,7 +104,7 @@ def test_mach2000_production_time_step():
     w = WL.mach2000_initial()
     prob = O.Problem(**w.problem_kwargs())
     dt = O.time_step(prob, O.max_speed(prob, w.U), 'production', 0.6)
-    assert dt == pytest.approx(GOLD['mach2000_dt']['value'], rel=2e-5)
+    assert dt == pytest.approx(GOLD['mach2000_dt']['value'], rel=2e-5, abs=0)
 
 
 @pytest.mark.parametrize("table,mk,n", [('table2_euler1d', WL.paper_euler1d, 20),
@@ -115,5 +117,5 @@ def test_interface_basis_reproduces_euler_tables(table, mk, n):
     U = _run(w, GOLD[table]['gamma0'], basis='interface')
     e = np.abs(U[0] - w.U[0])
     _, l1, linf = _row(table, n)
-    assert e.max() == pytest.approx(linf, rel=REL)
-    assert e.mean() == pytest.approx(l1, rel=REL)
+    assert e.max() == pytest.approx(linf, rel=REL, abs=0)
+    assert e.mean() == pytest.approx(l1, rel=REL, abs=0)
