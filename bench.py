@@ -12,6 +12,10 @@ HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
+The default warm-up (30 steps) takes the GPU past its ramp: the first ten
+steps of a fresh process run about 15% slower than the steady state, which
+is reached after about twenty.
+
 Prints ONE JSON line. ``value`` = cell-stage updates per second (cells x 3 x
 steps / wall time) in FP64. The FP32 form of the same workload is reported in
 ``fp32``. ``roofline`` covers the dominant kernel (the fused 2D Euler stage
@@ -448,7 +452,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=30)
-    ap.add_argument('--warmup', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=30)
     ap.add_argument('--n', type=int, default=2048)
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle baseline')
     ap.add_argument('--no-fp32', action='store_true', help='skip the FP32 form')
